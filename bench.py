@@ -1,0 +1,162 @@
+"""Benchmark: train+test points/s of one fit + predict (mean and variance) of
+the Mercer GP on one MI355X, split-BF16 mixed path beside the plain FP64 GPU
+path, plus the FP64 CPU oracle on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (default): p = 4, n = 8 (M = 4096), N = N_* = 1e6, x ~ U[-1,1]^4,
+y = exp(-|x|^2) + cos(3 x1 x2) + N(0, 0.05^2), eps = 1, alpha = 1.2.  A step is
+gp_fit + gp_predict(mean, var) with inputs resident in HBM; value =
+(N + N_*) / seconds per step.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "train+test points/s at p=4,M=4096 (mixed vs FP64 GPU); p50/p99 request latency"
+PEAK_BF16 = 2.5e15      # dense MFMA, MI355X
+PEAK_FP64 = 78.6e12     # FP64 MFMA, MI355X
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--N", type=int, default=None)
+    ap.add_argument("--Ns", type=int, default=None)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison path")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-target-s", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def run_path(ctx, torch, P, dev, precision, steps, warmup):
+    from paper_2403_12797_amd import binding as B
+    x, y, xs = dev
+    mean = torch.empty(P.Ns, dtype=torch.float64, device="cuda")
+    var = torch.empty(P.Ns, dtype=torch.float64, device="cuda")
+
+    def step():
+        m = ctx.fit(x, y, p=P.p, n=P.n, sigma=P.sigma, eps=P.eps, alpha=P.alpha, precision=precision)
+        ctx.predict(m, xs, mean, var)
+        torch.cuda.synchronize()
+        m.free()
+
+    for _ in range(warmup):
+        step()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    return dt, prof, (mean, var)
+
+
+def cpu_baseline(P_full, target_s):
+    """The FP64 oracle (as it is) on a bounded sample of the same workload."""
+    from oracle import mercer_gp as o
+    from paper_2403_12797_amd import workloads as wl
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
+    except Exception:
+        cores = os.cpu_count() or 1
+
+    def timed(Nsamp, Nssamp):
+        P = wl.config(P_full.name.split("_")[0], N=Nsamp, Ns=Nssamp)
+        t0 = time.perf_counter()
+        f = o.fit(P.x, P.y, P.sigma, P.eps, P.alpha, P.n)
+        o.predict(f, P.xs)
+        return time.perf_counter() - t0
+
+    n0, ns0 = 8192, 1024
+    t = timed(n0, ns0)
+    scale = max(1.0, min(16.0, target_s / max(t, 1e-3)))
+    n1, ns1 = int(n0 * scale) // 1024 * 1024, int(ns0 * scale) // 128 * 128
+    t1 = timed(n1, ns1) if scale > 1.5 else t
+    if scale <= 1.5:
+        n1, ns1 = n0, ns0
+    return {"value": (n1 + ns1) / t1, "unit": "points/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{P_full.name} shape (p={P_full.p}, n={P_full.n}, M={P_full.M}) at N={n1}, N*={ns1}: "
+                      f"oracle fit (Gram, LU) + predict (mean, variance) in {t1:.2f} s, FP64 numpy/scipy; "
+                      f"includes the fixed M^3 factorisation, so it understates the oracle's large-N rate"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU design is described "
+              f"in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2403_12797_amd import binding as B
+    from paper_2403_12797_amd import workloads as wl
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    P = wl.config(a.config, N=a.N, Ns=a.Ns)
+    dev = tuple(torch.from_numpy(np.ascontiguousarray(v)).cuda() for v in (P.x, P.y, P.xs))
+    torch.cuda.synchronize()
+    ctx = B.Context(0)
+    print(f"[bench] {P.name} N={P.N} Ns={P.Ns} M={P.M}: mixed path", file=sys.stderr, flush=True)
+    dt_mx, prof_mx, _ = run_path(ctx, torch, P, dev, B.PREC_MIXED, a.steps, a.warmup)
+    print(f"[bench] mixed {dt_mx * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    fp64 = None
+    if not a.no_fp64:
+        k64 = max(1, min(a.steps, 2))
+        dt64, prof64, _ = run_path(ctx, torch, P, dev, B.PREC_FP64, k64, 1)
+        print(f"[bench] fp64 {dt64 * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+        g64 = prof64["gram"][0] / k64
+        fp64 = {"value": (P.N + P.Ns) / dt64, "ms_per_step": dt64 * 1e3, "steps": k64,
+                "gram_frac_fp64_peak": (P.N * P.M * (P.M + 1)) / (g64 * 1e-3) / PEAK_FP64,
+                "phases_ms": {k: round(v[0] / k64, 3) for k, v in prof64.items() if v[1]}}
+    ctx.close()
+
+    steps = a.steps
+    g_ms, g_cnt = prof_mx["gram"]
+    launches_per_step = g_cnt / steps
+    avg_launch_ms = g_ms / g_cnt
+    flops_per_step = P.N * P.M * (P.M + 1)            # useful Gram flops (upper triangle, mul+add)
+    achieved = flops_per_step / (g_ms / steps * 1e-3)
+    issued = 6.0 * achieved * (2.0 * 65536 * (((P.M + 255) // 256) * ((P.M + 255) // 256 + 1) // 2)) / \
+        (P.M * (P.M + 1))
+    pv_ms = prof_mx["predict"][0] / steps
+    out = {
+        "metric": METRIC, "value": (P.N + P.Ns) / dt_mx, "unit": "points/s", "n_gpus": 1, "steps": steps,
+        "warmup": a.warmup, "ms_per_step": dt_mx * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"{P.name}: p={P.p}, n={P.n}, M={P.M}, N={P.N}, N*={P.Ns}, "
+                               f"x~U[-1,1]^4, y=exp(-|x|^2)+cos(3x1x2)+N(0,0.05^2), eps=1, alpha=1.2; "
+                               f"fit + predict(mean, var), split-BF16 MFMA (3 terms, 6 products Gram; "
+                               f"2 terms, 3 products variance), FP64 Cholesky + 1 refinement",
+                   "precision": "mixed"},
+        "roofline": {"kernel": "gram_mixed_kernel", "bound": "mfma", "achieved": achieved / 1e12,
+                     "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_BF16,
+                     "traffic": None, "launches_per_step": launches_per_step,
+                     "avg_launch_ms": avg_launch_ms, "algorithmic_flops_per_step": flops_per_step,
+                     "mfma_issue_frac": issued / PEAK_BF16,
+                     "predict_kernel_frac": (P.Ns * P.M * (P.M + 1)) / (pv_ms * 1e-3) / PEAK_BF16},
+        "phases_ms": {k: round(v[0] / steps, 3) for k, v in prof_mx.items() if v[1]},
+        "fp64_path": fp64,
+        "cpu_baseline": None if a.no_cpu else cpu_baseline(P, a.cpu_target_s),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

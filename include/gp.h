@@ -1,0 +1,190 @@
+/*
+ * gp.h - C ABI of libmercergp, a decomposed-kernel (Mercer) Gaussian-process
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * Method: D. Carminati, "Parallel Gaussian Process with Kernel Approximation
+ * in CUDA" (arXiv 2403.12797), Sec. 2.  The squared-exponential kernel
+ * (eq. 13, ARD form eq. 17) is replaced by its truncated Mercer expansion
+ * k ~ Phi Lambda Phi^T (eq. 7) over all M = n^p tensor-product multi-indices
+ * (eqs. 18-20), with 1-D eigenpairs of eqs. 14-16.  The FAGP posterior
+ * (eqs. 10-12) is computed in the algebraically equal weight-space form
+ *     A  = Phi^T Phi + sigma^2 Lambda^-1        (= sigma^2 Lambda_bar, eq. 10)
+ *     w  = A^-1 Phi^T y
+ *     mu_* = Phi_* w                             (eq. 11)
+ *     v_*  = sigma^2 diag(Phi_* A^-1 Phi_*^T)    (diagonal of eq. 12)
+ * (W of eq. 11 simplifies to Phi_* A^-1 Phi^T; I - A^-1 Phi^T Phi equals
+ * sigma^2 A^-1 Lambda^-1.)  The prior mean is zero and v_* is the variance of
+ * the latent f_* (no added sigma^2).
+ *
+ * Conventions for every entry point
+ *  - Return value: gp_status; 0 is success, negative is an error.  No C++
+ *    exception crosses the ABI.  gp_last_error() gives a message for the last
+ *    failing call on the calling thread.
+ *  - Arrays named "device" are device pointers in the memory of the context's
+ *    GPU (for example torch tensors); arrays named "host" are host pointers.
+ *    The caller owns every array it passes; the library never frees them.
+ *  - x arrays are row-major float64 [count * p] (sample i, dimension j at
+ *    i*p + j); y / mean / var are float64 [count].
+ *  - "stream" is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is ordered on that stream.
+ *  - Multi-indices (eq. 18) are enumerated in C order: index
+ *    m = sum_j k_j n^(p-1-j), the last input dimension varying fastest.  Only
+ *    the layout of w (gp_model_get) depends on that order.
+ */
+#ifndef MERCERGP_GP_H
+#define MERCERGP_GP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GP_OK = 0,
+  GP_PENDING = 1,      /* gp_poll: request not finished yet                     */
+  GP_EINVAL = -1,      /* invalid argument (checked before any device work)     */
+  GP_ENOMEM = -2,      /* device allocation failed or request can never fit     */
+  GP_ENOTSPD = -3,     /* Cholesky found a non-positive pivot (message: column) */
+  GP_EDEVICE = -4,     /* HIP runtime error                                     */
+  GP_ENOTFOUND = -5,   /* unknown request id                                    */
+  GP_ECANCELED = -6    /* request dropped because the context is shutting down  */
+} gp_status;
+
+typedef enum {
+  GP_PREC_FP64 = 0,    /* every contraction in FP64 (FP64 MFMA)                 */
+  GP_PREC_MIXED = 1    /* Gram / predict as split-BF16 MFMA products with FP32
+                          accumulation; FP64 factorisation, solves, one FP64
+                          iterative-refinement step on w                         */
+} gp_precision;
+
+/* Limits enforced by validation. */
+#define GP_MAX_P 8
+#define GP_MAX_N 64
+#define GP_MAX_M 16384
+
+/* Problem parameters (Sec. 2.1 problem statement; eqs. 13-20).
+ *  p      input dimension, 1..GP_MAX_P
+ *  n      eigenvalues per dimension, 1..GP_MAX_N; M = n^p <= GP_MAX_M
+ *  sigma  noise standard deviation, > 0 (Sigma_n = sigma^2 I, Sec. 2.2)
+ *  eps    host [p]: ARD length scales eps_j > 0 (eq. 17)
+ *  alpha  host [p]: global scale factors rho_j > 0 (eqs. 14-16, 19-20)
+ *  precision  gp_precision                                                   */
+typedef struct {
+  int32_t p;
+  int32_t n;
+  double sigma;
+  const double *eps;
+  const double *alpha;
+  int32_t precision;
+} gp_params;
+
+typedef struct gp_ctx gp_ctx;      /* one GPU: streams, workspace, scheduler   */
+typedef struct gp_model gp_model;  /* device-resident fitted model             */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device
+ * memory the served path (gp_submit) may hold at once; 0 means 90% of the
+ * free memory at creation.  Errors: GP_EINVAL (bad device), GP_EDEVICE.     */
+gp_status gp_ctx_create(int device, size_t hbm_budget_bytes, gp_ctx **out);
+
+/* Destroy a context: stops its scheduler (pending requests end as
+ * GP_ECANCELED) and frees its workspace.  Models created from it must be
+ * freed first.  NULL is accepted.                                           */
+gp_status gp_ctx_destroy(gp_ctx *ctx);
+
+/* Fit: Lambda (eq. 20), A = Phi^T Phi + sigma^2 Lambda^-1 and b = Phi^T y with
+ * Phi generated on the fly (eqs. 15, 19), Cholesky A = L L^T, w = A^-1 b
+ * (mixed precision: plus one FP64 refinement step), and L^-1 for the
+ * variance.  x: device [N*p], y: device [N], N >= 1.  The call returns once
+ * the model is ready (it waits on `stream`); x and y may then be freed.
+ * *out_model receives a new model owned by the caller (gp_model_free).
+ * Errors: GP_EINVAL (parameters, N < 1, NULL pointers), GP_ENOMEM,
+ * GP_ENOTSPD (numerically non-SPD A), GP_EDEVICE.                          */
+gp_status gp_fit(gp_ctx *ctx, const gp_params *params, const double *x, const double *y,
+                 int64_t N, void *stream, gp_model **out_model);
+
+/* Predict: mean = Phi_* w (eq. 11) and var = sigma^2 diag(Phi_* A^-1 Phi_*^T)
+ * (diagonal of eq. 12).  xs: device [Ns*p]; mean, var: device [Ns]; either
+ * output may be NULL (not computed).  Ns = 0 is a no-op.  The work is
+ * enqueued on `stream` and the call returns without waiting; outputs are
+ * valid once the stream has reached this point.  Precision follows the
+ * model.  Errors: GP_EINVAL, GP_ENOMEM, GP_EDEVICE.                          */
+gp_status gp_predict(gp_ctx *ctx, const gp_model *model, const double *xs, int64_t Ns,
+                     double *mean, double *var, void *stream);
+
+/* Free a model (waits for the device work that uses it).  NULL accepted.  */
+gp_status gp_model_free(gp_model *model);
+
+/* Model shape: any output pointer may be NULL.                              */
+gp_status gp_model_info(const gp_model *model, int32_t *p, int32_t *n, int64_t *M,
+                        int32_t *precision, double *sigma);
+
+/* Copy a model array to host memory (synchronous).  `count` is the capacity
+ * of host_out in doubles and must be at least the array size:
+ *   GP_MODEL_W        [M]    weights w, C-order multi-index
+ *   GP_MODEL_LAMBDA   [M]    Lambda_m, eq. 20
+ *   GP_MODEL_A        [M*M]  A = Phi^T Phi + sigma^2 Lambda^-1 (row-major,
+ *                            both triangles), as accumulated on the GPU
+ *   GP_MODEL_B        [M]    Phi^T y
+ *   GP_MODEL_L        [M*M]  Cholesky factor L (row-major, upper part zero)
+ *   GP_MODEL_LINV     [M*M]  L^-1 (row-major, upper part zero)
+ * Errors: GP_EINVAL (unknown array, count too small), GP_EDEVICE.          */
+enum { GP_MODEL_W = 0, GP_MODEL_LAMBDA = 1, GP_MODEL_A = 2, GP_MODEL_B = 3, GP_MODEL_L = 4,
+       GP_MODEL_LINV = 5 };
+gp_status gp_model_get(const gp_model *model, int32_t what, double *host_out, int64_t count);
+
+/* Served path: asynchronous requests with continuous batching.
+ *  kind   GP_REQ_FIT (x, y, N -> model), GP_REQ_PREDICT (model, xs, Ns ->
+ *         mean/var), GP_REQ_FIT_PREDICT (both; the model is kept only if
+ *         model_out is requested at poll time, else freed).
+ * All arrays are device arrays as above and must stay valid until gp_poll
+ * has returned a final (non-PENDING) status for the request.  Requests are
+ * admitted when their device footprint fits the context's HBM budget; work
+ * of admitted requests overlaps on the device.
+ * gp_submit errors: GP_EINVAL, GP_ENOMEM (footprint exceeds the whole budget).
+ * gp_poll: waits up to wait_us microseconds (0 = just check, <0 = forever);
+ * returns GP_PENDING, or the request's final status exactly once, after
+ * which the id is retired (GP_ENOTFOUND afterwards).  For FIT kinds the
+ * fitted model is stored to *model_out if model_out is not NULL.          */
+enum { GP_REQ_FIT = 0, GP_REQ_PREDICT = 1, GP_REQ_FIT_PREDICT = 2 };
+typedef struct {
+  int32_t kind;
+  gp_params params;           /* FIT kinds; eps/alpha copied at submit        */
+  const double *x, *y;        /* device [N*p], [N]                            */
+  int64_t N;
+  const gp_model *model;      /* PREDICT                                      */
+  const double *xs;           /* device [Ns*p]                                */
+  int64_t Ns;
+  double *mean, *var;         /* device [Ns], either may be NULL              */
+} gp_request;
+gp_status gp_submit(gp_ctx *ctx, const gp_request *req, int64_t *req_id);
+gp_status gp_poll(gp_ctx *ctx, int64_t req_id, int32_t wait_us, gp_model **model_out);
+
+/* Profiling: device time per phase, measured with HIP events recorded on
+ * the stream each phase runs on.  gp_profile_enable(ctx, 1) clears the totals
+ * and starts recording for later gp_fit / gp_predict calls of this context
+ * (one call at a time per context while enabled); gp_profile_read waits for
+ * the recorded events and returns the total milliseconds and the number of
+ * timed intervals of one phase.  Errors: GP_EINVAL (phase), GP_EDEVICE.     */
+enum { GP_PH_GRAM = 0,          /* fused Phi + Gram kernels (a3)            */
+       GP_PH_GRAM_REDUCE = 1,   /* split-K reduction into A                 */
+       GP_PH_PHIT = 2,          /* b = Phi^T y                              */
+       GP_PH_CHOL = 3,          /* Cholesky                                 */
+       GP_PH_TRTRI = 4,         /* L^-1                                     */
+       GP_PH_SOLVE = 5,         /* solves and the refinement step           */
+       GP_PH_SPLIT = 6,         /* BF16 split of L^-1 (mixed)               */
+       GP_PH_PREDICT = 7,       /* fused predict / variance kernels (a5)    */
+       GP_PH_PREDICT_MEAN = 8,  /* FP64 mean kernel (FP64 path)             */
+       GP_PH_PREDICT_REDUCE = 9,
+       GP_PH_COUNT = 10 };
+gp_status gp_profile_enable(gp_ctx *ctx, int32_t on);
+gp_status gp_profile_read(gp_ctx *ctx, int32_t phase, double *total_ms, int64_t *count);
+
+/* Message describing the last failing call on this thread ("" if none).   */
+const char *gp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MERCERGP_GP_H */

@@ -1,0 +1,212 @@
+"""ctypes binding of libmercergp (C ABI in include/gp.h).
+
+Argument marshalling only: every step of the fit and the prediction runs in
+the library's HIP kernels.  Device arrays are torch CUDA tensors (float64,
+contiguous); streams are torch streams.  There is no CPU fallback: if the
+library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmercergp.so")
+
+GP_OK, GP_PENDING = 0, 1
+GP_EINVAL, GP_ENOMEM, GP_ENOTSPD, GP_EDEVICE, GP_ENOTFOUND, GP_ECANCELED = -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "GP_OK", 1: "GP_PENDING", -1: "GP_EINVAL", -2: "GP_ENOMEM", -3: "GP_ENOTSPD",
+                -4: "GP_EDEVICE", -5: "GP_ENOTFOUND", -6: "GP_ECANCELED"}
+PREC_FP64, PREC_MIXED = 0, 1
+MODEL_W, MODEL_LAMBDA, MODEL_A, MODEL_B, MODEL_L, MODEL_LINV = range(6)
+REQ_FIT, REQ_PREDICT, REQ_FIT_PREDICT = 0, 1, 2
+MAX_P, MAX_N, MAX_M = 8, 64, 16384
+
+EXPORTED = ["gp_ctx_create", "gp_ctx_destroy", "gp_fit", "gp_predict", "gp_model_free", "gp_model_info",
+            "gp_model_get", "gp_submit", "gp_poll", "gp_last_error", "gp_profile_enable", "gp_profile_read"]
+PHASES = ["gram", "gram_reduce", "phiT", "chol", "trtri", "solve", "split", "predict", "predict_mean",
+          "predict_reduce"]
+
+
+class GpParams(C.Structure):
+    _fields_ = [("p", C.c_int32), ("n", C.c_int32), ("sigma", C.c_double),
+                ("eps", C.POINTER(C.c_double)), ("alpha", C.POINTER(C.c_double)),
+                ("precision", C.c_int32)]
+
+
+class GpRequest(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("params", GpParams), ("x", C.c_void_p), ("y", C.c_void_p),
+                ("N", C.c_int64), ("model", C.c_void_p), ("xs", C.c_void_p), ("Ns", C.c_int64),
+                ("mean", C.c_void_p), ("var", C.c_void_p)]
+
+
+class GpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} not built; run python -m paper_2403_12797_amd.build")
+    lib = C.CDLL(path)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    sig = {
+        "gp_ctx_create": (i32, [C.c_int, C.c_size_t, C.POINTER(vp)]),
+        "gp_ctx_destroy": (i32, [vp]),
+        "gp_fit": (i32, [vp, C.POINTER(GpParams), vp, vp, i64, vp, C.POINTER(vp)]),
+        "gp_predict": (i32, [vp, vp, vp, i64, vp, vp, vp]),
+        "gp_model_free": (i32, [vp]),
+        "gp_model_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), C.POINTER(i32), dp]),
+        "gp_model_get": (i32, [vp, i32, dp, i64]),
+        "gp_submit": (i32, [vp, C.POINTER(GpRequest), C.POINTER(i64)]),
+        "gp_poll": (i32, [vp, i64, i32, C.POINTER(vp)]),
+        "gp_last_error": (C.c_char_p, []),
+        "gp_profile_enable": (i32, [vp, i32]),
+        "gp_profile_read": (i32, [vp, i32, dp, C.POINTER(i64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().gp_last_error().decode()
+
+
+def _check(st: int) -> int:
+    if st < 0:
+        raise GpError(st, last_error())
+    return st
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_params(p, n, sigma, eps, alpha, precision=PREC_FP64):
+    import numpy as np
+    e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (p,)))
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha, dtype=np.float64), (p,)))
+    prm = GpParams(p, n, float(sigma), e.ctypes.data_as(C.POINTER(C.c_double)),
+                   a.ctypes.data_as(C.POINTER(C.c_double)), precision)
+    prm._keep = (e, a)
+    return prm
+
+
+class Model:
+    def __init__(self, handle: C.c_void_p):
+        self.handle = handle
+
+    def info(self):
+        p, n, M, prec, sig = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32(), C.c_double()
+        _check(load().gp_model_info(self.handle, C.byref(p), C.byref(n), C.byref(M), C.byref(prec), C.byref(sig)))
+        return {"p": p.value, "n": n.value, "M": M.value, "precision": prec.value, "sigma": sig.value}
+
+    def get(self, what: int):
+        import numpy as np
+        M = self.info()["M"]
+        size = M * M if what in (MODEL_A, MODEL_L, MODEL_LINV) else M
+        out = np.empty(size, dtype=np.float64)
+        _check(load().gp_model_get(self.handle, what, out.ctypes.data_as(C.POINTER(C.c_double)), size))
+        return out.reshape(M, M) if size == M * M else out
+
+    def free(self):
+        if self.handle:
+            load().gp_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.handle = C.c_void_p()
+        _check(load().gp_ctx_create(device, hbm_budget_bytes, C.byref(self.handle)))
+
+    def close(self):
+        if self.handle:
+            load().gp_ctx_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def profile(self, on: bool = True):
+        _check(load().gp_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{phase name: (total ms, intervals)} of the recorded phases."""
+        out = {}
+        for k, name in enumerate(PHASES):
+            ms, cnt = C.c_double(), C.c_int64()
+            _check(load().gp_profile_read(self.handle, k, C.byref(ms), C.byref(cnt)))
+            out[name] = (ms.value, cnt.value)
+        return out
+
+    def fit(self, x, y, *, p, n, sigma, eps, alpha, precision=PREC_FP64, stream=None) -> Model:
+        prm = make_params(p, n, sigma, eps, alpha, precision)
+        out = C.c_void_p()
+        N = y.shape[0] if y is not None else 0
+        _check(load().gp_fit(self.handle, C.byref(prm), _ptr(x), _ptr(y), N, _stream(stream), C.byref(out)))
+        return Model(out)
+
+    def predict(self, model: Model, xs, mean=None, var=None, stream=None):
+        Ns = xs.shape[0] if xs is not None else 0
+        _check(load().gp_predict(self.handle, model.handle, _ptr(xs), Ns, _ptr(mean), _ptr(var),
+                                 _stream(stream)))
+        return mean, var
+
+    def submit(self, kind, *, x=None, y=None, params=None, model=None, xs=None, mean=None, var=None) -> int:
+        req = GpRequest()
+        req.kind = kind
+        if params is not None:
+            req.params = params
+        req.x = _ptr(x)
+        req.y = _ptr(y)
+        req.N = y.shape[0] if y is not None else 0
+        req.model = model.handle if model is not None else None
+        req.xs = _ptr(xs)
+        req.Ns = xs.shape[0] if xs is not None else 0
+        req.mean = _ptr(mean)
+        req.var = _ptr(var)
+        rid = C.c_int64()
+        _check(load().gp_submit(self.handle, C.byref(req), C.byref(rid)))
+        return rid.value
+
+    def poll(self, rid: int, wait_us: int = 0, want_model: bool = False):
+        """Returns (status, Model or None).  Raises GpError on a failed request."""
+        out = C.c_void_p()
+        st = load().gp_poll(self.handle, rid, wait_us, C.byref(out) if want_model else None)
+        if st < 0:
+            raise GpError(st, last_error())
+        return st, (Model(out) if want_model and out.value else None)

@@ -1,0 +1,432 @@
+// C ABI of libmercergp: validation, model lifetime, fit / predict drivers.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "kernels.h"
+#include "runtime.h"
+
+namespace mgp {
+
+thread_local std::string g_last_error;
+
+gp_status fail(gp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(_e == hipErrorOutOfMemory ? GP_ENOMEM : GP_EDEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(_e), __FILE__, __LINE__);                   \
+  } while (0)
+
+gp_status validate_params(const gp_params* prm, int64_t* M_out) {
+  if (!prm) return fail(GP_EINVAL, "params is NULL");
+  if (prm->p < 1 || prm->p > GP_MAX_P) return fail(GP_EINVAL, "p=%d outside 1..%d", prm->p, GP_MAX_P);
+  if (prm->n < 1 || prm->n > GP_MAX_N) return fail(GP_EINVAL, "n=%d outside 1..%d", prm->n, GP_MAX_N);
+  int64_t M = 1;
+  for (int j = 0; j < prm->p; ++j) {
+    M *= prm->n;
+    if (M > GP_MAX_M) return fail(GP_EINVAL, "M=n^p exceeds %d (n=%d, p=%d)", GP_MAX_M, prm->n, prm->p);
+  }
+  if (!(prm->sigma > 0.0) || !isfinite(prm->sigma)) return fail(GP_EINVAL, "sigma must be finite and > 0");
+  if (!prm->eps || !prm->alpha) return fail(GP_EINVAL, "eps/alpha must be host arrays of length p");
+  for (int j = 0; j < prm->p; ++j) {
+    if (!(prm->eps[j] > 0.0) || !isfinite(prm->eps[j])) return fail(GP_EINVAL, "eps[%d] must be finite and > 0", j);
+    if (!(prm->alpha[j] > 0.0) || !isfinite(prm->alpha[j]))
+      return fail(GP_EINVAL, "alpha[%d] must be finite and > 0", j);
+  }
+  if (prm->precision != GP_PREC_FP64 && prm->precision != GP_PREC_MIXED)
+    return fail(GP_EINVAL, "unknown precision %d", prm->precision);
+  *M_out = M;
+  return GP_OK;
+}
+
+// Device bytes a fitted model holds (used by admission control too).
+size_t model_bytes(int64_t M, int precision) {
+  const size_t MM = (size_t)M * M;
+  size_t b = kTabSize * 8 + 4 * M * 8 + 3 * MM * 8 + (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8 + 256;
+  if (precision == GP_PREC_MIXED) b += 2 * (size_t)M * linv_pitch((int)M) * 2;
+  return b;
+}
+
+// Transient device bytes of a fit / predict.
+size_t fit_workspace_bytes(int64_t N, int64_t M, int precision) {
+  size_t g = precision == GP_PREC_MIXED ? (size_t)gram_mixed_part_elems(N, (int)M, nullptr) * 4
+                                        : (size_t)gram_f64_part_elems(N, (int)M, nullptr) * 8;
+  size_t v = (size_t)phiT_part_elems(N, (int)M) * 8 + (size_t)N * 8 + 4 * (size_t)M * 8 +
+             (size_t)ceil_div(M, 256) * M * 8;
+  return g + v + 1024;
+}
+
+size_t predict_workspace_bytes(int64_t Ns, int64_t M, int precision) {
+  if (Ns <= 0) return 0;
+  return (precision == GP_PREC_MIXED ? (size_t)predict_mixed_part_elems(Ns, (int)M, nullptr)
+                                     : (size_t)predict_part_elems(Ns, (int)M, nullptr)) *
+             8 +
+         256;
+}
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+void prof_mark(Prof* p, int phase, bool begin, hipStream_t s) {
+  if (!p || !p->on) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  hipEventRecord(e, s);
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (begin) {
+    if (p->open[phase]) hipEventDestroy(p->open[phase]);
+    p->open[phase] = e;
+  } else if (p->open[phase]) {
+    p->pending[phase].emplace_back(p->open[phase], e);
+    p->open[phase] = nullptr;
+  } else {
+    hipEventDestroy(e);
+  }
+}
+
+void model_release(gp_model* m, hipStream_t s, bool sync_device) {
+  if (!m) return;
+  if (m->base) {
+    hipSetDevice(m->ctx->device);
+    if (sync_device) hipDeviceSynchronize();
+    hipFreeAsync(m->base, s);
+    if (sync_device) hipStreamSynchronize(s);
+  }
+  delete m;
+}
+
+gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t s, gp_model** out) {
+  gp_model* m = new gp_model();
+  m->ctx = ctx;
+  m->p = prm->p;
+  m->n = prm->n;
+  m->M = M;
+  m->precision = prm->precision;
+  m->sigma = prm->sigma;
+  for (int j = 0; j < prm->p; ++j) {
+    m->eps[j] = prm->eps[j];
+    m->alpha[j] = prm->alpha[j];
+  }
+  const size_t MM = (size_t)M * M;
+  const size_t sizes[] = {kTabSize * 8, (size_t)M * 8, (size_t)M * 8, MM * 8, MM * 8, MM * 8,
+                          (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8, (size_t)M * 8, (size_t)M * 8,
+                          64, prm->precision == GP_PREC_MIXED ? 2 * (size_t)M * linv_pitch((int)M) * 2 : 0};
+  size_t total = 0;
+  for (size_t s : sizes) total += align_up(s);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMallocAsync(&m->base, total, s);
+  if (e != hipSuccess) {
+    delete m;
+    return fail(e == hipErrorOutOfMemory ? GP_ENOMEM : GP_EDEVICE, "model allocation of %zu bytes: %s", total,
+                hipGetErrorString(e));
+  }
+  m->bytes = total;
+  char* b = (char*)m->base;
+  size_t o = 0;
+  auto take = [&](size_t s) {
+    void* r = b + o;
+    o += align_up(s);
+    return r;
+  };
+  m->tab = (double*)take(sizes[0]);
+  m->lam = (double*)take(sizes[1]);
+  m->reg = (double*)take(sizes[2]);
+  m->A = (double*)take(sizes[3]);
+  m->L = (double*)take(sizes[4]);
+  m->Linv = (double*)take(sizes[5]);
+  m->Dinv = (double*)take(sizes[6]);
+  m->w = (double*)take(sizes[7]);
+  m->b = (double*)take(sizes[8]);
+  m->flags = (int*)take(sizes[9]);
+  m->linv_pieces = prm->precision == GP_PREC_MIXED ? (__bf16*)take(sizes[10]) : nullptr;
+  *out = m;
+  return GP_OK;
+}
+
+// Enqueue the whole fit on stream s.  ws must hold fit_workspace_bytes().
+// flags[0] = Cholesky info, flags[1] = non-finite input.
+void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void* ws, hipStream_t s) {
+  const int p = m->p, n = m->n, M = (int)m->M;
+  EigArgs a;
+  memset(&a, 0, sizeof(a));
+  a.p = p;
+  a.n = n;
+  a.sigma = m->sigma;
+  for (int j = 0; j < p; ++j) {
+    a.eps[j] = m->eps[j];
+    a.alpha[j] = m->alpha[j];
+  }
+  char* wb = (char*)ws;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    void* r = wb + o;
+    o += align_up(bytes);
+    return r;
+  };
+  const size_t gbytes = m->precision == GP_PREC_MIXED ? (size_t)gram_mixed_part_elems(N, M, nullptr) * 4
+                                                      : (size_t)gram_f64_part_elems(N, M, nullptr) * 8;
+  void* gpart = take(gbytes);
+  double* vpart = (double*)take((size_t)phiT_part_elems(N, M) * 8);
+  double* resid = (double*)take((size_t)N * 8);
+  double* z = (double*)take((size_t)M * 8);
+  double* r = (double*)take((size_t)M * 8);
+  double* d = (double*)take((size_t)M * 8);
+  double* ltpart = (double*)take((size_t)ceil_div(M, 256) * M * 8);
+
+  Prof* pr = &m->ctx->prof;
+  hipMemsetAsync(m->flags, 0, 64, s);
+  launch_check_finite(x, N * p, m->flags + 1, s);
+  launch_check_finite(y, N, m->flags + 1, s);
+  launch_eig_tables(a, m->tab, m->lam, m->reg, M, s);
+  // a3: A = Phi^T Phi + sigma^2 Lambda^-1, b = Phi^T y
+  if (m->precision == GP_PREC_MIXED)
+    launch_gram_mixed(x, N, p, n, M, m->tab, m->reg, (float*)gpart, m->A, s, pr);
+  else
+    launch_gram_f64(x, N, p, n, M, m->tab, m->reg, (double*)gpart, m->A, s, pr);
+  prof_mark(pr, GP_PH_PHIT, true, s);
+  launch_phiT_vec(x, y, N, p, n, M, m->tab, vpart, nullptr, nullptr, m->b, s);
+  prof_mark(pr, GP_PH_PHIT, false, s);
+  // a4: L L^T = A, L^-1, w = L^-T L^-1 b, one refinement with the FP64 residual
+  prof_mark(pr, GP_PH_CHOL, true, s);
+  hipMemcpyAsync(m->L, m->A, (size_t)M * M * 8, hipMemcpyDeviceToDevice, s);
+  launch_cholesky(m->L, M, m->Dinv, m->flags, s);
+  prof_mark(pr, GP_PH_CHOL, false, s);
+  prof_mark(pr, GP_PH_TRTRI, true, s);
+  launch_trtri(m->L, m->Dinv, m->Linv, M, m->flags, s);
+  prof_mark(pr, GP_PH_TRTRI, false, s);
+  prof_mark(pr, GP_PH_SOLVE, true, s);
+  launch_lower_matvec(m->Linv, m->b, z, M, s);
+  launch_lower_t_matvec(m->Linv, z, m->w, ltpart, M, s);
+  launch_phi_matvec(x, N, p, n, M, m->tab, m->w, y, resid, s);                 // y - Phi w
+  launch_phiT_vec(x, resid, N, p, n, M, m->tab, vpart, m->reg, m->w, r, s);    // Phi^T(y - Phi w) - reg*w
+  launch_lower_matvec(m->Linv, r, z, M, s);
+  launch_lower_t_matvec(m->Linv, z, d, ltpart, M, s);
+  launch_axpy(m->w, d, M, s);
+  prof_mark(pr, GP_PH_SOLVE, false, s);
+  if (m->precision == GP_PREC_MIXED) {
+    prof_mark(pr, GP_PH_SPLIT, true, s);
+    launch_split_linv(m->Linv, m->linv_pieces, M, s);
+    prof_mark(pr, GP_PH_SPLIT, false, s);
+  }
+}
+
+void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* mean, double* var, void* ws,
+                     hipStream_t s) {
+  if (Ns <= 0) return;
+  const int p = m->p, n = m->n, M = (int)m->M;
+  const double s2 = m->sigma * m->sigma;
+  Prof* pr = &m->ctx->prof;
+  if (m->precision == GP_PREC_MIXED) {
+    launch_predict_mixed(xs, Ns, p, n, M, m->tab, m->linv_pieces, m->w, s2, (double*)ws, mean, var, s, pr);
+  } else {
+    if (mean) {
+      prof_mark(pr, GP_PH_PREDICT_MEAN, true, s);
+      launch_phi_matvec(xs, Ns, p, n, M, m->tab, m->w, nullptr, mean, s);
+      prof_mark(pr, GP_PH_PREDICT_MEAN, false, s);
+    }
+    if (var) launch_predict_var_f64(xs, Ns, p, n, M, m->tab, m->Linv, s2, (double*)ws, var, s, pr);
+  }
+}
+
+}  // namespace mgp
+
+using namespace mgp;
+
+extern "C" {
+
+const char* gp_last_error(void) { return g_last_error.c_str(); }
+
+gp_status gp_ctx_create(int device, size_t hbm_budget_bytes, gp_ctx** out) {
+  if (!out) return fail(GP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0) return fail(GP_EDEVICE, "no HIP device: %s", hipGetErrorString(e));
+  if (device < 0 || device >= count) return fail(GP_EINVAL, "device %d not in 0..%d", device, count - 1);
+  HIP_TRY(hipSetDevice(device));
+  HIP_TRY(configure_kernels());
+  size_t freeb = 0, totalb = 0;
+  HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+  gp_ctx* c = new gp_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)freeb);
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  gp_status st = scheduler_start(c);
+  if (st != GP_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return GP_OK;
+}
+
+gp_status gp_ctx_destroy(gp_ctx* ctx) {
+  if (!ctx) return GP_OK;
+  scheduler_stop(ctx);
+  delete ctx;
+  return GP_OK;
+}
+
+gp_status gp_fit(gp_ctx* ctx, const gp_params* params, const double* x, const double* y, int64_t N, void* stream,
+                 gp_model** out_model) {
+  if (!ctx || !out_model) return fail(GP_EINVAL, "ctx/out_model is NULL");
+  *out_model = nullptr;
+  int64_t M = 0;
+  gp_status st = validate_params(params, &M);
+  if (st != GP_OK) return st;
+  if (N < 1) return fail(GP_EINVAL, "N=%lld must be >= 1", (long long)N);
+  if (!x || !y) return fail(GP_EINVAL, "x/y is NULL");
+  if (fault_take(ctx, "oom")) return fail(GP_ENOMEM, "injected allocation failure");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  gp_model* m = nullptr;
+  st = model_alloc(ctx, params, M, s, &m);
+  if (st != GP_OK) return st;
+  void* ws = nullptr;
+  const size_t wsb = fit_workspace_bytes(N, M, params->precision);
+  hipError_t e = hipMallocAsync(&ws, wsb, s);
+  if (e != hipSuccess) {
+    gp_model_free(m);
+    return fail(e == hipErrorOutOfMemory ? GP_ENOMEM : GP_EDEVICE, "fit workspace of %zu bytes: %s", wsb,
+                hipGetErrorString(e));
+  }
+  enqueue_fit(m, x, y, N, ws, s);
+  hipFreeAsync(ws, s);
+  int flags[2] = {0, 0};
+  e = hipMemcpyAsync(flags, m->flags, sizeof(flags), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    gp_model_free(m);
+    return fail(GP_EDEVICE, "fit: %s", hipGetErrorString(e));
+  }
+  if (flags[1]) {
+    gp_model_free(m);
+    return fail(GP_EINVAL, "x or y holds a non-finite value");
+  }
+  if (fault_take(ctx, "chol")) flags[0] = 1;
+  if (flags[0]) {
+    gp_model_free(m);
+    return fail(GP_ENOTSPD, "Cholesky: non-positive pivot at column %d", flags[0] - 1);
+  }
+  *out_model = m;
+  return GP_OK;
+}
+
+gp_status gp_predict(gp_ctx* ctx, const gp_model* model, const double* xs, int64_t Ns, double* mean, double* var,
+                     void* stream) {
+  if (!ctx || !model) return fail(GP_EINVAL, "ctx/model is NULL");
+  if (Ns < 0) return fail(GP_EINVAL, "Ns=%lld must be >= 0", (long long)Ns);
+  if (Ns == 0 || (!mean && !var)) return GP_OK;
+  if (!xs) return fail(GP_EINVAL, "xs is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = nullptr;
+  const size_t wsb = predict_workspace_bytes(Ns, model->M, model->precision);
+  HIP_TRY(hipMallocAsync(&ws, wsb, s));
+  enqueue_predict(model, xs, Ns, mean, var, ws, s);
+  HIP_TRY(hipFreeAsync(ws, s));
+  HIP_TRY(hipGetLastError());
+  return GP_OK;
+}
+
+gp_status gp_profile_enable(gp_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(GP_EINVAL, "ctx is NULL");
+  Prof& p = ctx->prof;
+  std::lock_guard<std::mutex> lk(p.mu);
+  for (int k = 0; k < GP_PH_COUNT; ++k) {
+    for (auto& pr : p.pending[k]) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+    p.pending[k].clear();
+    if (p.open[k]) hipEventDestroy(p.open[k]);
+    p.open[k] = nullptr;
+    p.ms[k] = 0.0;
+    p.count[k] = 0;
+  }
+  p.on = on != 0;
+  return GP_OK;
+}
+
+gp_status gp_profile_read(gp_ctx* ctx, int32_t phase, double* total_ms, int64_t* count) {
+  if (!ctx) return fail(GP_EINVAL, "ctx is NULL");
+  if (phase < 0 || phase >= GP_PH_COUNT) return fail(GP_EINVAL, "unknown phase %d", phase);
+  Prof& p = ctx->prof;
+  std::lock_guard<std::mutex> lk(p.mu);
+  for (auto& pr : p.pending[phase]) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventSynchronize(pr.second));
+    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    p.ms[phase] += ms;
+    p.count[phase] += 1;
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  p.pending[phase].clear();
+  if (total_ms) *total_ms = p.ms[phase];
+  if (count) *count = p.count[phase];
+  return GP_OK;
+}
+
+gp_status gp_model_free(gp_model* model) {
+  if (!model) return GP_OK;
+  model_release(model, nullptr, true);
+  return GP_OK;
+}
+
+gp_status gp_model_info(const gp_model* model, int32_t* p, int32_t* n, int64_t* M, int32_t* precision,
+                        double* sigma) {
+  if (!model) return fail(GP_EINVAL, "model is NULL");
+  if (p) *p = model->p;
+  if (n) *n = model->n;
+  if (M) *M = model->M;
+  if (precision) *precision = model->precision;
+  if (sigma) *sigma = model->sigma;
+  return GP_OK;
+}
+
+gp_status gp_model_get(const gp_model* model, int32_t what, double* host_out, int64_t count) {
+  if (!model || !host_out) return fail(GP_EINVAL, "model/host_out is NULL");
+  const int64_t M = model->M;
+  const double* src = nullptr;
+  int64_t len = 0;
+  bool lower = false;
+  switch (what) {
+    case GP_MODEL_W: src = model->w; len = M; break;
+    case GP_MODEL_LAMBDA: src = model->lam; len = M; break;
+    case GP_MODEL_A: src = model->A; len = M * M; break;
+    case GP_MODEL_B: src = model->b; len = M; break;
+    case GP_MODEL_L: src = model->L; len = M * M; lower = true; break;
+    case GP_MODEL_LINV: src = model->Linv; len = M * M; lower = true; break;
+    default: return fail(GP_EINVAL, "unknown model array %d", what);
+  }
+  if (count < len) return fail(GP_EINVAL, "count %lld < %lld", (long long)count, (long long)len);
+  HIP_TRY(hipSetDevice(model->ctx->device));
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(host_out, src, (size_t)len * 8, hipMemcpyDeviceToHost));
+  if (lower)
+    for (int64_t r = 0; r < M; ++r)
+      for (int64_t c = r + 1; c < M; ++c) host_out[r * M + c] = 0.0;
+  return GP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// Launchers of the libmercergp device kernels (all asynchronous on `s`).
+#pragma once
+
+#include "common.h"
+
+namespace mgp {
+
+struct EigArgs {
+  int p, n;
+  double sigma;
+  double eps[GP_MAX_P];
+  double alpha[GP_MAX_P];
+};
+
+// a1: per-dimension constants, recurrence coefficients and 1-D eigenvalues
+// into tab[kTabSize]; Lambda[M] (eq. 20) and reg[M] = sigma^2 / Lambda.
+void launch_eig_tables(const EigArgs& a, double* tab, double* lam, double* reg, int M, hipStream_t s);
+
+// out[i] = y ? y[i] - (Phi w)_i : (Phi w)_i, Phi generated on the fly from x
+// (the mean Phi_* w and the residual y - Phi w).
+void launch_phi_matvec(const double* x, int64_t N, int p, int n, int M, const double* tab,
+                       const double* w, const double* y, double* out, hipStream_t s);
+
+// out[m] = sum_i Phi[i,m] v[i] - (sub ? sub[m] * wsub[m] : 0), deterministic
+// two-pass reduction through `part` (see phiT_part_elems).
+int64_t phiT_part_elems(int64_t N, int M);
+void launch_phiT_vec(const double* x, const double* v, int64_t N, int p, int n, int M,
+                     const double* tab, double* part, const double* sub, const double* wsub,
+                     double* out, hipStream_t s);
+
+// a3 (FP64): A = Phi^T Phi + diag(reg), full symmetric M x M row-major.
+int64_t gram_f64_part_elems(int64_t N, int M, int* splitk_out);
+void launch_gram_f64(const double* x, int64_t N, int p, int n, int M, const double* tab,
+                     const double* reg, double* part, double* A, hipStream_t s, Prof* prof = nullptr);
+
+// a3 (mixed): split-BF16 MFMA Gram, FP32 accumulate, FP64 split-K reduce.
+int64_t gram_mixed_part_elems(int64_t N, int M, int* splitk_out);
+void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const double* tab,
+                       const double* reg, float* part, double* A, hipStream_t s, Prof* prof = nullptr);
+
+// a4: blocked Cholesky in place (lower), block inverses Dinv[M/64][64*64],
+// info (device int, 0 = ok, else failing column + 1).
+constexpr int kCholNb = 64;
+void launch_cholesky(double* A, int M, double* Dinv, int* info, hipStream_t s);
+// L^-1 (lower, upper part zero) from L and Dinv.
+void launch_trtri(const double* L, const double* Dinv, double* Linv, int M, const int* info,
+                  hipStream_t s);
+// z = Linv b ; w = Linv^T z  (both through `tmp`, M doubles)
+void launch_lower_matvec(const double* Linv, const double* b, double* z, int M, hipStream_t s);
+void launch_lower_t_matvec(const double* Linv, const double* z, double* w, double* part, int M,
+                           hipStream_t s);
+// w += d
+void launch_axpy(double* w, const double* d, int M, hipStream_t s);
+// Split of L^-1 into two bf16 terms (mixed predict): pieces[q][M][P] with
+// row pitch P = linv_pitch(M) (multiple of 16, padding columns zero).
+__host__ __device__ inline int linv_pitch(int M) { return (M + 15) & ~15; }
+void launch_split_linv(const double* Linv, __bf16* pieces, int M, hipStream_t s);
+
+// a5 variance: var[i] = sigma^2 || L^-1 phi_*(x_i) ||^2
+int64_t predict_part_elems(int64_t Ns, int M, int* groups_out);
+void launch_predict_var_f64(const double* xs, int64_t Ns, int p, int n, int M, const double* tab,
+                            const double* Linv, double sigma2, double* part, double* var,
+                            hipStream_t s, Prof* prof = nullptr);
+// a5 mixed: fused mean (FP64 dot with w) and split-BF16 variance.
+int64_t predict_mixed_part_elems(int64_t Ns, int M, int* groups_out);
+void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, const double* tab,
+                          const __bf16* linv_pieces, const double* w, double sigma2, double* part,
+                          double* mean, double* var, hipStream_t s, Prof* prof = nullptr);
+
+// Device check that every element of v[count] is finite; sets *flag = 1 if not.
+void launch_check_finite(const double* v, int64_t count, int* flag, hipStream_t s);
+
+// Raise the dynamic-LDS limit of the kernels that need more than 64 KB.
+hipError_t configure_kernels();
+
+}  // namespace mgp

@@ -1,0 +1,107 @@
+// Host-side runtime objects of libmercergp: context, model, served-request
+// scheduler.
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "common.h"
+
+struct gp_model {
+  gp_ctx* ctx = nullptr;
+  int p = 0, n = 0;
+  int64_t M = 0;
+  int precision = 0;
+  double sigma = 0.0;
+  double eps[GP_MAX_P] = {};
+  double alpha[GP_MAX_P] = {};
+  void* base = nullptr;  // one device allocation holding every array below
+  size_t bytes = 0;
+  double *tab = nullptr, *lam = nullptr, *reg = nullptr, *A = nullptr, *L = nullptr, *Linv = nullptr,
+         *Dinv = nullptr, *w = nullptr, *b = nullptr;
+  int* flags = nullptr;  // [0] Cholesky info, [1] non-finite input
+  __bf16* linv_pieces = nullptr;
+};
+
+namespace mgp {
+
+// One served request (see gp_submit).
+struct Request {
+  int64_t id = 0;
+  gp_request desc{};
+  double eps[GP_MAX_P] = {}, alpha[GP_MAX_P] = {};
+  size_t footprint = 0;   // device bytes held while in flight
+  size_t ws_bytes = 0;
+  gp_status status = GP_PENDING;
+  gp_model* model = nullptr;  // fitted model (FIT kinds)
+  void* ws = nullptr;
+  int slot = -1;
+  bool inject_chol = false;
+  double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  int* flags_host = nullptr;   // pinned copy of the model flags
+  Request* req = nullptr;
+};
+
+}  // namespace mgp
+
+namespace mgp {
+// Per-phase HIP-event timing (see gp_profile_enable).
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  hipEvent_t open[GP_PH_COUNT] = {};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[GP_PH_COUNT];
+  double ms[GP_PH_COUNT] = {};
+  int64_t count[GP_PH_COUNT] = {};
+};
+}  // namespace mgp
+
+struct gp_ctx {
+  int device = 0;
+  size_t budget = 0;
+  mgp::Prof prof;
+  // served path
+  std::mutex mu;
+  std::condition_variable cv_work;   // scheduler wake-up
+  std::condition_variable cv_done;   // poll wake-up
+  std::deque<mgp::Request*> queue;
+  std::map<int64_t, mgp::Request*> requests;
+  std::vector<mgp::Slot> slots;
+  size_t in_flight_bytes = 0;
+  int64_t next_id = 1;
+  bool stop = false;
+  std::thread thread;
+  // fault injection: names of failures to report for the next request(s)
+  std::string faults;
+};
+
+namespace mgp {
+gp_status fail(gp_status st, const char* fmt, ...);
+gp_status validate_params(const gp_params* prm, int64_t* M_out);
+size_t model_bytes(int64_t M, int precision);
+size_t fit_workspace_bytes(int64_t N, int64_t M, int precision);
+size_t predict_workspace_bytes(int64_t Ns, int64_t M, int precision);
+gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t s, gp_model** out);
+// Free a model's device memory stream-ordered on s (after a device-wide sync
+// if sync_device) and delete it.
+void model_release(gp_model* m, hipStream_t s, bool sync_device);
+void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void* ws, hipStream_t s);
+void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* mean, double* var, void* ws,
+                     hipStream_t s);
+gp_status scheduler_start(gp_ctx* ctx);
+void scheduler_stop(gp_ctx* ctx);
+// Consume one pending injected fault of this name (from MGP_FAULT or
+// gp_ctx_inject_fault); returns true if one was pending.
+bool fault_take(gp_ctx* ctx, const char* name);
+}  // namespace mgp

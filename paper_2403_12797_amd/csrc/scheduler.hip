@@ -1,0 +1,298 @@
+// Served path: gp_submit / gp_poll with continuous batching.
+//
+// A scheduler thread per context admits queued requests in arrival order as
+// soon as a stream slot is free and the request's device footprint fits the
+// context's HBM budget, enqueues its fit and/or predict on that slot's
+// stream (so the work of admitted requests overlaps on the GPU), and retires
+// requests whose completion event has fired.  Fitted models stay
+// device-resident and are handed to the caller at poll time.
+#include <chrono>
+#include <stdlib.h>
+#include <string.h>
+
+#include "runtime.h"
+
+namespace mgp {
+
+constexpr int kSlots = 4;
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool fault_take(gp_ctx* ctx, const char* name) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  std::string& f = ctx->faults;
+  const std::string key = std::string(name) + ",";
+  const size_t pos = f.find(key);
+  if (pos == std::string::npos) return false;
+  f.erase(pos, key.size());
+  return true;
+}
+
+// Release a finished request's transient resources (mu held).
+static void finish(gp_ctx* ctx, Request* r, gp_status st) {
+  r->status = st;
+  r->t_done = now_s();
+  hipStream_t s = r->slot >= 0 ? ctx->slots[r->slot].stream : nullptr;
+  if (r->ws) {
+    hipFreeAsync(r->ws, s);
+    r->ws = nullptr;
+  }
+  ctx->in_flight_bytes -= r->footprint;
+  if (st != GP_OK && r->model) {
+    model_release(r->model, s, false);
+    r->model = nullptr;
+  }
+}
+
+// Allocate and enqueue one admitted request on slot k (mu held).
+static void launch(gp_ctx* ctx, Request* r, int k) {
+  Slot& sl = ctx->slots[k];
+  const gp_request& d = r->desc;
+  r->slot = k;
+  hipError_t e = hipMallocAsync(&r->ws, r->ws_bytes ? r->ws_bytes : 256, sl.stream);
+  if (e != hipSuccess) {
+    r->ws = nullptr;
+    finish(ctx, r, GP_ENOMEM);
+    return;
+  }
+  const gp_model* pm = d.model;
+  if (d.kind != GP_REQ_PREDICT) {
+    gp_params prm = d.params;
+    prm.eps = r->eps;
+    prm.alpha = r->alpha;
+    int64_t M = 0;
+    validate_params(&prm, &M);
+    gp_status st = model_alloc(ctx, &prm, M, sl.stream, &r->model);
+    if (st != GP_OK) {
+      finish(ctx, r, st);
+      return;
+    }
+    enqueue_fit(r->model, d.x, d.y, d.N, r->ws, sl.stream);
+    hipMemcpyAsync(sl.flags_host, r->model->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, sl.stream);
+    pm = r->model;
+  } else {
+    sl.flags_host[0] = sl.flags_host[1] = 0;
+  }
+  if (d.kind != GP_REQ_FIT && d.Ns > 0 && (d.mean || d.var)) {
+    // predict workspace follows the fit workspace in the same block
+    const size_t fitb = d.kind == GP_REQ_FIT_PREDICT ? fit_workspace_bytes(d.N, pm->M, pm->precision) : 0;
+    enqueue_predict(pm, d.xs, d.Ns, d.mean, d.var, (char*)r->ws + ((fitb + 255) & ~(size_t)255), sl.stream);
+  }
+  hipEventRecord(sl.done, sl.stream);
+  r->t_admit = now_s();
+  sl.req = r;
+}
+
+static void scheduler_loop(gp_ctx* ctx) {
+  hipSetDevice(ctx->device);
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  while (true) {
+    // retire finished slots
+    bool retired = false;
+    int active = 0;
+    for (int k = 0; k < (int)ctx->slots.size(); ++k) {
+      Slot& sl = ctx->slots[k];
+      if (!sl.req) continue;
+      const hipError_t q = hipEventQuery(sl.done);
+      if (q == hipErrorNotReady) {
+        ++active;
+        continue;
+      }
+      Request* r = sl.req;
+      sl.req = nullptr;
+      gp_status st = GP_OK;
+      if (q != hipSuccess)
+        st = GP_EDEVICE;
+      else if (sl.flags_host[1])
+        st = GP_EINVAL;
+      else if (sl.flags_host[0] || r->inject_chol)
+        st = GP_ENOTSPD;
+      finish(ctx, r, st);
+      retired = true;
+    }
+    if (retired) ctx->cv_done.notify_all();
+    if (ctx->stop && ctx->queue.empty() && active == 0) break;
+    // admit in arrival order while a slot is free and memory fits
+    while (!ctx->queue.empty()) {
+      Request* r = ctx->queue.front();
+      if (ctx->stop) {
+        ctx->queue.pop_front();
+        r->status = GP_ECANCELED;
+        ctx->cv_done.notify_all();
+        continue;
+      }
+      int free_slot = -1;
+      for (int k = 0; k < (int)ctx->slots.size(); ++k)
+        if (!ctx->slots[k].req) {
+          free_slot = k;
+          break;
+        }
+      if (free_slot < 0 || ctx->in_flight_bytes + r->footprint > ctx->budget) break;
+      ctx->queue.pop_front();
+      ctx->in_flight_bytes += r->footprint;
+      launch(ctx, r, free_slot);
+      if (r->status != GP_PENDING) ctx->cv_done.notify_all();
+      else ++active;
+    }
+    if (active > 0)
+      ctx->cv_work.wait_for(lk, std::chrono::microseconds(50));
+    else if (!ctx->stop)
+      ctx->cv_work.wait(lk);
+  }
+}
+
+gp_status scheduler_start(gp_ctx* ctx) {
+  ctx->slots.resize(kSlots);
+  for (auto& sl : ctx->slots) {
+    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void**)&sl.flags_host, 16, hipHostMallocDefault) != hipSuccess)
+      return fail(GP_EDEVICE, "scheduler: stream/event/pinned allocation failed");
+  }
+  if (const char* f = getenv("MGP_FAULT")) {
+    ctx->faults = f;
+    if (!ctx->faults.empty() && ctx->faults.back() != ',') ctx->faults += ",";
+  }
+  ctx->thread = std::thread(scheduler_loop, ctx);
+  return GP_OK;
+}
+
+void scheduler_stop(gp_ctx* ctx) {
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->stop = true;
+  }
+  ctx->cv_work.notify_all();
+  if (ctx->thread.joinable()) ctx->thread.join();
+  hipDeviceSynchronize();
+  for (auto& kv : ctx->requests) {
+    Request* r = kv.second;
+    if (r->model) model_release(r->model, nullptr, false);
+    delete r;
+  }
+  hipStreamSynchronize(nullptr);
+  ctx->requests.clear();
+  for (auto& sl : ctx->slots) {
+    if (sl.stream) hipStreamDestroy(sl.stream);
+    if (sl.done) hipEventDestroy(sl.done);
+    if (sl.flags_host) hipHostFree(sl.flags_host);
+  }
+  ctx->slots.clear();
+}
+
+}  // namespace mgp
+
+using namespace mgp;
+
+extern "C" {
+
+gp_status gp_submit(gp_ctx* ctx, const gp_request* req, int64_t* req_id) {
+  if (!ctx || !req || !req_id) return fail(GP_EINVAL, "ctx/req/req_id is NULL");
+  *req_id = 0;
+  Request* r = new Request();
+  r->desc = *req;
+  int64_t M = 0;
+  int prec = 0;
+  if (req->kind == GP_REQ_FIT || req->kind == GP_REQ_FIT_PREDICT) {
+    gp_status st = validate_params(&req->params, &M);
+    if (st != GP_OK) {
+      delete r;
+      return st;
+    }
+    if (req->N < 1 || !req->x || !req->y) {
+      delete r;
+      return fail(GP_EINVAL, "FIT request needs x, y and N >= 1");
+    }
+    for (int j = 0; j < req->params.p; ++j) {
+      r->eps[j] = req->params.eps[j];
+      r->alpha[j] = req->params.alpha[j];
+    }
+    prec = req->params.precision;
+  } else if (req->kind == GP_REQ_PREDICT) {
+    if (!req->model) {
+      delete r;
+      return fail(GP_EINVAL, "PREDICT request needs a model");
+    }
+    M = req->model->M;
+    prec = req->model->precision;
+  } else {
+    delete r;
+    return fail(GP_EINVAL, "unknown request kind %d", req->kind);
+  }
+  if (req->kind != GP_REQ_FIT && req->Ns > 0 && (req->mean || req->var) && !req->xs) {
+    delete r;
+    return fail(GP_EINVAL, "predict part needs xs");
+  }
+  if (req->Ns < 0) {
+    delete r;
+    return fail(GP_EINVAL, "Ns must be >= 0");
+  }
+  size_t ws = 0, foot = 0;
+  if (req->kind != GP_REQ_PREDICT) {
+    ws += (fit_workspace_bytes(req->N, M, prec) + 255) & ~(size_t)255;
+    foot += model_bytes(M, prec);
+  }
+  if (req->kind != GP_REQ_FIT) ws += predict_workspace_bytes(req->Ns, M, prec);
+  foot += ws;
+  r->ws_bytes = ws;
+  r->footprint = foot;
+  if (foot > ctx->budget) {
+    const size_t budget = ctx->budget;
+    delete r;
+    return fail(GP_ENOMEM, "request needs %zu device bytes, budget is %zu", foot, budget);
+  }
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->stop) {
+      delete r;
+      return fail(GP_ECANCELED, "context is shutting down");
+    }
+    const std::string key = "chol,";
+    const size_t pos = ctx->faults.find(key);
+    if (pos != std::string::npos && req->kind != GP_REQ_PREDICT) {
+      ctx->faults.erase(pos, key.size());
+      r->inject_chol = true;
+    }
+    r->id = ctx->next_id++;
+    r->t_submit = now_s();
+    ctx->requests[r->id] = r;
+    ctx->queue.push_back(r);
+    *req_id = r->id;
+  }
+  ctx->cv_work.notify_one();
+  return GP_OK;
+}
+
+gp_status gp_poll(gp_ctx* ctx, int64_t req_id, int32_t wait_us, gp_model** model_out) {
+  if (!ctx) return fail(GP_EINVAL, "ctx is NULL");
+  if (model_out) *model_out = nullptr;
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  auto it = ctx->requests.find(req_id);
+  if (it == ctx->requests.end()) return fail(GP_ENOTFOUND, "unknown request id %lld", (long long)req_id);
+  Request* r = it->second;
+  if (r->status == GP_PENDING && wait_us != 0) {
+    auto done = [&] { return r->status != GP_PENDING; };
+    if (wait_us < 0)
+      ctx->cv_done.wait(lk, done);
+    else
+      ctx->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), done);
+  }
+  if (r->status == GP_PENDING) return GP_PENDING;
+  const gp_status st = r->status;
+  if (r->model) {
+    if (model_out && st == GP_OK) {
+      *model_out = r->model;
+    } else {
+      model_release(r->model, nullptr, false);
+    }
+    r->model = nullptr;
+  }
+  ctx->requests.erase(it);
+  delete r;
+  if (st < 0) return fail(st, "request %lld failed with status %d", (long long)req_id, (int)st);
+  return st;
+}
+
+}  // extern "C"

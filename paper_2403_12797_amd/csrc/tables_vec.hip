@@ -1,0 +1,240 @@
+// a1 eigen tables and the FP64 matrix-free Phi / Phi^T vector products.
+#include "kernels.h"
+
+namespace mgp {
+
+// ---------------------------------------------------------------- a1
+// Per-dimension scalars of eq. 14 (delta^2 = alpha^2/2 (beta^2-1)), the
+// eigenvalues of eq. 16 and the normalised Hermite recurrence coefficients.
+__global__ void eig_dim_kernel(EigArgs a, double* __restrict__ tab) {
+  const int t = threadIdx.x;
+  if (t < a.p) {
+    const double eps = a.eps[t], al = a.alpha[t];
+    const double r = 2.0 * eps / al;
+    const double beta = sqrt(sqrt(1.0 + r * r));
+    const double d2 = al * al * 0.5 * (beta * beta - 1.0);
+    double* dc = tab + kTabDim + t * kDimStride;
+    dc[0] = al * beta;
+    dc[1] = d2;
+    dc[2] = sqrt(beta);
+    dc[3] = 0.0;
+    const double D = al * al + d2 + eps * eps;
+    const double q = eps * eps / D;
+    double lam = sqrt(al * al / D);
+    for (int k = 0; k < a.n; ++k) {
+      tab[kTabLam1 + t * GP_MAX_N + k] = lam;
+      lam *= q;
+    }
+  }
+  if (t < GP_MAX_N) {
+    tab[kTabRc1 + t] = t > 0 ? sqrt(2.0 / (t + 1.0)) : 0.0;
+    tab[kTabRc2 + t] = t > 0 ? sqrt((double)t / (t + 1.0)) : 0.0;
+  }
+}
+
+// Lambda_m = prod_j lambda_{j,k_j(m)} (eq. 20) and the ridge sigma^2/Lambda_m.
+__global__ void eig_lambda_kernel(int p, int n, int M, double sigma2, const double* __restrict__ tab,
+                                  double* __restrict__ lam, double* __restrict__ reg) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  int rem = m;
+  double v = 1.0;
+  for (int j = p - 1; j >= 0; --j) {
+    v *= tab[kTabLam1 + j * GP_MAX_N + rem % n];
+    rem /= n;
+  }
+  lam[m] = v;
+  reg[m] = sigma2 / v;
+}
+
+void launch_eig_tables(const EigArgs& a, double* tab, double* lam, double* reg, int M, hipStream_t s) {
+  hipLaunchKernelGGL(eig_dim_kernel, dim3(1), dim3(64), 0, s, a, tab);
+  hipLaunchKernelGGL(eig_lambda_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, a.p, a.n, M,
+                     a.sigma * a.sigma, tab, lam, reg);
+}
+
+// ---------------------------------------------------------------- helpers
+// Fill the 1-D eigenfunction table of `cnt` samples starting at s0 into LDS.
+// Layout "sample-fastest": T[(j*n + k) * ld + i] = phi_{j,k+1}(x_{s0+i, j}).
+// Rows past N are zero.  Called by the whole block; caller syncs.
+template <typename T>
+__device__ __forceinline__ void fill_tab_sf(const double* __restrict__ x, int64_t N, int p, int n,
+                                            int64_t s0, int cnt, int ld, const double* __restrict__ tab,
+                                            T* __restrict__ out) {
+  const double* rc1 = tab + kTabRc1;
+  const double* rc2 = tab + kTabRc2;
+  for (int t = threadIdx.x; t < cnt * p; t += blockDim.x) {
+    const int i = t % cnt, j = t / cnt;
+    const int64_t row = s0 + i;
+    T* o = out + (j * n) * ld + i;
+    if (row < N) {
+      const double* dc = tab + kTabDim + j * kDimStride;
+      phi_1d<double, T>(x[row * p + j], dc[0], dc[1], dc[2], rc1, rc2, n, o, ld);
+    } else {
+      for (int k = 0; k < n; ++k) o[k * ld] = (T)0;
+    }
+  }
+}
+
+// Same table, "column-fastest": T[i * ld + j*n + k].
+__device__ __forceinline__ void fill_tab_cf(const double* __restrict__ x, int64_t N, int p, int n,
+                                            int64_t s0, int cnt, int ld, const double* __restrict__ tab,
+                                            double* __restrict__ out) {
+  const double* rc1 = tab + kTabRc1;
+  const double* rc2 = tab + kTabRc2;
+  for (int t = threadIdx.x; t < cnt * p; t += blockDim.x) {
+    const int i = t % cnt, j = t / cnt;
+    const int64_t row = s0 + i;
+    double* o = out + i * ld + j * n;
+    if (row < N) {
+      const double* dc = tab + kTabDim + j * kDimStride;
+      phi_1d<double, double>(x[row * p + j], dc[0], dc[1], dc[2], rc1, rc2, n, o, 1);
+    } else {
+      for (int k = 0; k < n; ++k) o[k] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Phi w
+// Block = 4 waves, 64 samples (one per lane).  Wave q walks the column
+// prefixes m_hi = m / n with m_hi % 4 == q; the last digit loops inside, so
+// each element costs one multiply and one FMA.  Wave partials are summed in
+// fixed order.
+constexpr int kMvRows = 64;
+
+__global__ void __launch_bounds__(256) phi_matvec_kernel(const double* __restrict__ x, int64_t N, int p,
+                                                         int n, int M, const double* __restrict__ tab,
+                                                         const double* __restrict__ w,
+                                                         const double* __restrict__ y,
+                                                         double* __restrict__ out) {
+  extern __shared__ double sm[];
+  double* T = sm;                                 // [p*n][64]
+  double* red = sm + p * n * kMvRows;             // [4][64]
+  const int64_t s0 = (int64_t)blockIdx.x * kMvRows;
+  fill_tab_sf<double>(x, N, p, n, s0, kMvRows, kMvRows, tab, T);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nhi = M / n;
+  double acc = 0.0;
+  int dig[GP_MAX_P];
+  for (int hi = wv; hi < nhi; hi += 4) {
+    // prefix product over dims 0..p-2 (digits of hi)
+    int rem = hi;
+    for (int j = p - 2; j >= 0; --j) {
+      dig[j] = rem % n;
+      rem /= n;
+    }
+    double pre = 1.0;
+    for (int j = 0; j < p - 1; ++j) pre *= T[(j * n + dig[j]) * kMvRows + lane];
+    const double* Tl = T + ((p - 1) * n) * kMvRows + lane;
+    const double* wl = w + (int64_t)hi * n;
+    for (int k = 0; k < n; ++k) acc = fma(pre * Tl[k * kMvRows], wl[k], acc);
+  }
+  red[wv * kMvRows + lane] = acc;
+  __syncthreads();
+  if (wv == 0) {
+    const double sum = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
+    const int64_t row = s0 + lane;
+    if (row < N) out[row] = y ? y[row] - sum : sum;
+  }
+}
+
+void launch_phi_matvec(const double* x, int64_t N, int p, int n, int M, const double* tab,
+                       const double* w, const double* y, double* out, hipStream_t s) {
+  if (N <= 0) return;
+  const size_t lds = (size_t)(p * n * kMvRows + 4 * kMvRows) * sizeof(double);
+  hipLaunchKernelGGL(phi_matvec_kernel, dim3(ceil_div(N, kMvRows)), dim3(256), lds, s, x, N, p, n, M, tab,
+                     w, y, out);
+}
+
+// ---------------------------------------------------------------- Phi^T v
+// Grid (column blocks of 256, sample chunks of kTvChunk).  Thread = column;
+// the table is column-fastest so lanes (consecutive columns) read distinct
+// or broadcast LDS words.  Partials part[chunk][M] are reduced in chunk order.
+constexpr int kTvChunk = 2048;
+constexpr int kTvSub = 32;
+
+int64_t phiT_part_elems(int64_t N, int M) { return ceil_div(N, kTvChunk) * (int64_t)M; }
+
+__global__ void __launch_bounds__(256) phiT_part_kernel(const double* __restrict__ x,
+                                                        const double* __restrict__ v, int64_t N, int p,
+                                                        int n, int M, const double* __restrict__ tab,
+                                                        double* __restrict__ part) {
+  extern __shared__ double sm[];
+  const int ld = p * n + 1;
+  double* T = sm;                      // [kTvSub][ld]
+  double* V = sm + kTvSub * ld;        // [kTvSub]
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.y * kTvChunk;
+  int off[GP_MAX_P];
+  {
+    int rem = m < M ? m : 0;
+    for (int j = p - 1; j >= 0; --j) {
+      off[j] = j * n + rem % n;
+      rem /= n;
+    }
+  }
+  double acc = 0.0;
+  for (int64_t s0 = c0; s0 < c0 + kTvChunk && s0 < N; s0 += kTvSub) {
+    __syncthreads();
+    fill_tab_cf(x, N, p, n, s0, kTvSub, ld, tab, T);
+    if (threadIdx.x < kTvSub) V[threadIdx.x] = (s0 + threadIdx.x < N) ? v[s0 + threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int i = 0; i < kTvSub; ++i) {
+      const double* Ti = T + i * ld;
+      double ph = Ti[off[0]];
+      for (int j = 1; j < p; ++j) ph *= Ti[off[j]];
+      acc = fma(ph, V[i], acc);
+    }
+  }
+  if (m < M) part[blockIdx.y * (int64_t)M + m] = acc;
+}
+
+__global__ void reduce_cols_kernel(const double* __restrict__ part, int64_t chunks, int M,
+                                   const double* __restrict__ sub, const double* __restrict__ wsub,
+                                   double* __restrict__ out) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  double s = 0.0;
+  for (int64_t c = 0; c < chunks; ++c) s += part[c * M + m];
+  if (sub) s -= sub[m] * wsub[m];
+  out[m] = s;
+}
+
+void launch_phiT_vec(const double* x, const double* v, int64_t N, int p, int n, int M, const double* tab,
+                     double* part, const double* sub, const double* wsub, double* out, hipStream_t s) {
+  const int64_t chunks = ceil_div(N, kTvChunk);
+  const int ld = p * n + 1;
+  const size_t lds = (size_t)(kTvSub * ld + kTvSub) * sizeof(double);
+  hipLaunchKernelGGL(phiT_part_kernel, dim3(ceil_div(M, 256), chunks), dim3(256), lds, s, x, v, N, p, n, M,
+                     tab, part);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part, chunks, M, sub, wsub,
+                     out);
+}
+
+// ---------------------------------------------------------------- input checks
+__global__ void check_finite_kernel(const double* __restrict__ v, int64_t count, int* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(v[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
+void launch_check_finite(const double* v, int64_t count, int* flag, hipStream_t s) {
+  if (count <= 0) return;
+  int64_t blocks = ceil_div(count, 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(check_finite_kernel, dim3(blocks), dim3(256), 0, s, v, count, flag);
+}
+
+// ---------------------------------------------------------------- small vector ops
+__global__ void axpy_kernel(double* __restrict__ w, const double* __restrict__ d, int M) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < M) w[m] += d[m];
+}
+
+void launch_axpy(double* w, const double* d, int M, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, w, d, M);
+}
+
+}  // namespace mgp

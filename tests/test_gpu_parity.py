@@ -1,0 +1,189 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle
+on the same seeded inputs.
+
+Tolerances (normwise relative, ||got - want||_2 / ||want||_2 per result vector):
+  FP64 path: 1e-10 on mean, variance and w.
+  Mixed path (split-BF16 Gram/predict, FP64 factorisation, one FP64
+  refinement step): 1e-5 on the mean, 1e-4 on the variance.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mercer_gp as o
+from paper_2403_12797_amd import binding as B
+from paper_2403_12797_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL_MEAN_MIXED = 1e-5
+TOL_VAR_MIXED = 1e-4
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_cuda):
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def gpu_fit_predict(torch, ctx, P, precision):
+    print(f"[case] {P.name} precision={precision} N={P.N} Ns={P.Ns} M={P.M}", flush=True)
+    x, y, xs = dev(torch, P.x), dev(torch, P.y), dev(torch, P.xs)
+    m = ctx.fit(x, y, p=P.p, n=P.n, sigma=P.sigma, eps=P.eps, alpha=P.alpha, precision=precision)
+    mean = torch.empty(P.Ns, dtype=torch.float64, device="cuda")
+    var = torch.empty(P.Ns, dtype=torch.float64, device="cuda")
+    ctx.predict(m, xs, mean, var)
+    torch.cuda.synchronize()
+    return m, mean.cpu().numpy(), var.cpu().numpy()
+
+
+def oracle_fit_predict(P):
+    f = o.fit(P.x, P.y, P.sigma, P.eps, P.alpha, P.n)
+    mean, var = o.predict(f, P.xs)
+    return f, mean, var
+
+
+def check(P, got, want, precision, extra=""):
+    m, gmean, gvar = got
+    f, omean, ovar = want
+    e_mean, e_var = rel(gmean, omean), rel(gvar, ovar)
+    w = m.get(B.MODEL_W)
+    e_w = rel(w, f.w)
+    print(f"[err] {P.name} prec={precision} mean={e_mean:.3e} var={e_var:.3e} w={e_w:.3e} {extra}", flush=True)
+    if precision == B.PREC_FP64:
+        assert e_mean <= TOL64 and e_var <= TOL64 and e_w <= TOL64
+    else:
+        assert e_mean <= TOL_MEAN_MIXED and e_var <= TOL_VAR_MIXED
+    return e_mean, e_var
+
+
+@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED])
+def test_c1_full(torch_cuda, ctx, precision):
+    P = wl.config("c1")
+    got = gpu_fit_predict(torch_cuda, ctx, P, precision)
+    want = oracle_fit_predict(P)
+    check(P, got, want, precision)
+    lam = got[0].get(B.MODEL_LAMBDA)
+    assert rel(lam, want[0].lam) <= 1e-14
+
+
+def test_c1_stages_fp64(torch_cuda, ctx):
+    """Per-stage parity: Lambda, A = Phi^T Phi + sigma^2 Lambda^-1, b = Phi^T y,
+    and L L^T = A, L^-1 L = I."""
+    P = wl.config("c1")
+    m, _, _ = gpu_fit_predict(torch_cuda, ctx, P, B.PREC_FP64)
+    f = o.fit(P.x, P.y, P.sigma, P.eps, P.alpha, P.n)
+    assert rel(m.get(B.MODEL_A), f.A) <= 1e-13
+    assert rel(m.get(B.MODEL_B), f.b) <= 1e-13
+    L = m.get(B.MODEL_L)
+    assert np.allclose(np.triu(L, 1), 0.0)
+    assert rel(L @ L.T, f.A) <= 1e-13
+    Li = m.get(B.MODEL_LINV)
+    assert np.abs(Li @ L - np.eye(P.M)).max() <= 1e-10
+
+
+@pytest.mark.parametrize("seed,p,n,N,Ns", [
+    (1, 1, 1, 1, 1),          # smallest problem
+    (2, 1, 7, 5, 3),          # M > N
+    (3, 2, 5, 257, 65),       # ragged tails
+    (4, 2, 12, 1000, 300),    # M = 144: two 128-tiles, ragged
+    (5, 3, 6, 3000, 1000),    # M = 216
+    (6, 4, 5, 2000, 777),     # M = 625
+    (7, 5, 3, 4097, 129),     # M = 243
+    (8, 1, 40, 600, 100),     # long 1-D expansion
+    (9, 8, 2, 1500, 200),     # p = 8, M = 256
+    (10, 3, 11, 5000, 513),   # M = 1331 (several 256-tiles, ragged)
+])
+@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED])
+def test_random_shapes(torch_cuda, ctx, seed, p, n, N, Ns, precision):
+    P = wl.random_problem(seed, p, n, N, Ns)
+    got = gpu_fit_predict(torch_cuda, ctx, P, precision)
+    want = oracle_fit_predict(P)
+    check(P, got, want, precision)
+
+
+@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED])
+def test_c2_shape(torch_cuda, ctx, precision):
+    """p = 3, n = 8 (M = 512), x ~ N(0, I): N reduced to 20000 for the oracle."""
+    P = wl.config("c2", N=20_000, Ns=4_000)
+    got = gpu_fit_predict(torch_cuda, ctx, P, precision)
+    check(P, got, oracle_fit_predict(P), precision)
+
+
+@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED])
+def test_c3_shape_reduced(torch_cuda, ctx, precision):
+    """p = 4, n = 8 (M = 4096), alpha = 1.2: N reduced to 30000 for the oracle."""
+    P = wl.config("c3", N=30_000, Ns=3_000)
+    got = gpu_fit_predict(torch_cuda, ctx, P, precision)
+    check(P, got, oracle_fit_predict(P), precision)
+
+
+def test_empty_predict_and_null_outputs(torch_cuda, ctx):
+    torch = torch_cuda
+    P = wl.random_problem(11, 2, 4, 100, 10)
+    m, mean, var = gpu_fit_predict(torch, ctx, P, B.PREC_FP64)
+    xs = dev(torch, P.xs)
+    ctx.predict(m, xs[:0], None, None)                         # Ns = 0
+    only_mean = torch.empty(P.Ns, dtype=torch.float64, device="cuda")
+    ctx.predict(m, xs, only_mean, None)
+    only_var = torch.empty(P.Ns, dtype=torch.float64, device="cuda")
+    ctx.predict(m, xs, None, only_var)
+    torch.cuda.synchronize()
+    assert np.array_equal(only_mean.cpu().numpy(), mean)
+    assert np.array_equal(only_var.cpu().numpy(), var)
+
+
+def test_invalid_arguments(torch_cuda, ctx):
+    torch = torch_cuda
+    x = torch.zeros((10, 2), dtype=torch.float64, device="cuda")
+    y = torch.zeros(10, dtype=torch.float64, device="cuda")
+    bad = [dict(p=0, n=4), dict(p=2, n=0), dict(p=2, n=65), dict(p=9, n=2), dict(p=2, n=200),
+           dict(p=3, n=26)]  # 26^3 > 16384
+    for kw in bad:
+        with pytest.raises(B.GpError) as ei:
+            ctx.fit(x, y, sigma=0.1, eps=1.0, alpha=1.0, **kw)
+        assert ei.value.status == B.GP_EINVAL
+    for sig, e, a in [(0.0, 1.0, 1.0), (-1.0, 1.0, 1.0), (float("nan"), 1.0, 1.0), (0.1, 0.0, 1.0),
+                      (0.1, 1.0, -2.0), (0.1, float("inf"), 1.0)]:
+        with pytest.raises(B.GpError) as ei:
+            ctx.fit(x, y, p=2, n=3, sigma=sig, eps=e, alpha=a)
+        assert ei.value.status == B.GP_EINVAL
+    with pytest.raises(B.GpError):
+        ctx.fit(x, y, p=2, n=3, sigma=0.1, eps=1.0, alpha=1.0, precision=7)
+    xn = x.clone()
+    xn[3, 1] = float("nan")
+    with pytest.raises(B.GpError) as ei:
+        ctx.fit(xn, y, p=2, n=3, sigma=0.1, eps=1.0, alpha=1.0)
+    assert ei.value.status == B.GP_EINVAL and "non-finite" in str(ei.value)
+    yn = y.clone()
+    yn[0] = float("inf")
+    with pytest.raises(B.GpError):
+        ctx.fit(x, yn, p=2, n=3, sigma=0.1, eps=1.0, alpha=1.0)
+
+
+def test_deterministic_repeat(torch_cuda, ctx):
+    """Same inputs twice give bitwise-equal results (fixed reduction orders)."""
+    P = wl.random_problem(12, 3, 6, 20000, 2000)
+    a = gpu_fit_predict(torch_cuda, ctx, P, B.PREC_MIXED)
+    b = gpu_fit_predict(torch_cuda, ctx, P, B.PREC_MIXED)
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
