@@ -63,8 +63,9 @@ size_t model_bytes(int64_t M, int precision) {
 }
 
 // Transient device bytes of a fit / predict.
-size_t fit_workspace_bytes(int64_t N, int64_t M, int precision) {
-  size_t g = precision == GP_PREC_MIXED ? (size_t)gram_mixed_part_elems(N, (int)M, nullptr) * 4
+size_t fit_workspace_bytes(int64_t N, int p, int n, int64_t M, int precision) {
+  size_t g = precision == GP_PREC_MIXED ? (size_t)gram_mixed_part_elems(N, (int)M, nullptr) * 4 +
+                                              (size_t)gram_mixed_table_elems(N, p, n) * 4 + 256
                                         : (size_t)gram_f64_part_elems(N, (int)M, nullptr) * 8;
   size_t v = (size_t)phiT_part_elems(N, (int)M) * 8 + (size_t)N * 8 + 4 * (size_t)M * 8 +
              (size_t)ceil_div(M, 256) * M * 8;
@@ -180,6 +181,7 @@ void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void*
   const size_t gbytes = m->precision == GP_PREC_MIXED ? (size_t)gram_mixed_part_elems(N, M, nullptr) * 4
                                                       : (size_t)gram_f64_part_elems(N, M, nullptr) * 8;
   void* gpart = take(gbytes);
+  float* tab32 = m->precision == GP_PREC_MIXED ? (float*)take((size_t)gram_mixed_table_elems(N, p, n) * 4) : nullptr;
   double* vpart = (double*)take((size_t)phiT_part_elems(N, M) * 8);
   double* resid = (double*)take((size_t)N * 8);
   double* z = (double*)take((size_t)M * 8);
@@ -194,7 +196,7 @@ void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void*
   launch_eig_tables(a, m->tab, m->lam, m->reg, M, s);
   // a3: A = Phi^T Phi + sigma^2 Lambda^-1, b = Phi^T y
   if (m->precision == GP_PREC_MIXED)
-    launch_gram_mixed(x, N, p, n, M, m->tab, m->reg, (float*)gpart, m->A, s, pr);
+    launch_gram_mixed(x, N, p, n, M, m->tab, m->reg, (float*)gpart, tab32, m->A, s, pr);
   else
     launch_gram_f64(x, N, p, n, M, m->tab, m->reg, (double*)gpart, m->A, s, pr);
   prof_mark(pr, GP_PH_PHIT, true, s);
@@ -301,7 +303,7 @@ gp_status gp_fit(gp_ctx* ctx, const gp_params* params, const double* x, const do
   st = model_alloc(ctx, params, M, s, &m);
   if (st != GP_OK) return st;
   void* ws = nullptr;
-  const size_t wsb = fit_workspace_bytes(N, M, params->precision);
+  const size_t wsb = fit_workspace_bytes(N, params->p, params->n, M, params->precision);
   hipError_t e = hipMallocAsync(&ws, wsb, s);
   if (e != hipSuccess) {
     gp_model_free(m);

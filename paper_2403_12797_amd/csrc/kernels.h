@@ -34,9 +34,12 @@ void launch_gram_f64(const double* x, int64_t N, int p, int n, int M, const doub
                      const double* reg, double* part, double* A, hipStream_t s, Prof* prof = nullptr);
 
 // a3 (mixed): split-BF16 MFMA Gram, FP32 accumulate, FP64 split-K reduce.
+// tab32 holds gram_mixed_table_elems() floats of workspace (1-D tables).
 int64_t gram_mixed_part_elems(int64_t N, int M, int* splitk_out);
+int64_t gram_mixed_table_elems(int64_t N, int p, int n);
 void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const double* tab,
-                       const double* reg, float* part, double* A, hipStream_t s, Prof* prof = nullptr);
+                       const double* reg, float* part, float* tab32, double* A, hipStream_t s,
+                       Prof* prof = nullptr);
 
 // a4: blocked Cholesky in place (lower), block inverses Dinv[M/64][64*64],
 // info (device int, 0 = ok, else failing column + 1).

@@ -46,15 +46,40 @@ __device__ __forceinline__ void split2(float a, float b, uint32_t& h, uint32_t& 
 }
 
 // ================================================================ a3 mixed Gram
-// Work-group: rows I*256..+256 and columns J*256 + h*128..+128 (half h of
-// the J-block) of Phi^T Phi, I <= J, over one chunk of samples.  256 threads =
-// 4 waves in a 2 (rows) x 2 (cols) grid, each owning 128 x 64 outputs =
-// 4 x 2 MFMA 32x32 blocks.
-// Stage = 16 samples.  Every thread generates one I-block column for the 16
-// samples and (off-diagonal tiles) half of one J-half column: products of the
-// FP64 1-D tables, one rounding to FP32, three BF16 terms stored in LDS as
-// [term][column slot][16 samples].  LDS is double-buffered, so the MFMAs of
-// stage t and the generation of stage t+1 interleave between barriers.
+// Pre-pass: the 1-D eigenfunctions of every sample, computed in FP64 and
+// stored as FP32 in stage-contiguous blocks of 16 samples:
+//   tab32[s][j*n + k][16]  (s = sample / 16), zero for samples >= N.
+constexpr int kGmKC = 16;
+
+__global__ void phi1d_table_kernel(const double* __restrict__ x, int64_t N, int p, int n,
+                                   const double* __restrict__ tab, float* __restrict__ out, int64_t nstage) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (stage, dim, sample-in-stage)
+  if (u >= nstage * p * kGmKC) return;
+  const int i = (int)(u % kGmKC);
+  const int j = (int)((u / kGmKC) % p);
+  const int64_t st = u / ((int64_t)kGmKC * p);
+  const int64_t row = st * kGmKC + i;
+  float* o = out + (st * p * n + (int64_t)j * n) * kGmKC + i;
+  if (row < N) {
+    const double* dc = tab + kTabDim + j * kDimStride;
+    phi_1d<double, float>(x[row * p + j], dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, kGmKC);
+  } else {
+    for (int k = 0; k < n; ++k) o[k * kGmKC] = 0.0f;
+  }
+}
+
+// Gram work-group: rows I*256..+256 and columns J*256 + h*128..+128 (half h
+// of the J-block) of Phi^T Phi, I <= J, over one chunk of samples.  256
+// threads = 4 waves in a 2 (rows) x 2 (cols) grid, each owning 128 x 64
+// outputs = 4 x 2 MFMA 32x32 blocks.
+// Stage = 16 samples.  Per stage every thread generates one I-block column
+// for the 16 samples and (off-diagonal tiles) half of one J-half column: the
+// product of the P FP32 1-D table values, split into three BF16 terms and
+// stored in LDS as [term][column slot][16 samples] (slot pitch padded against
+// bank conflicts).  LDS is double-buffered and the MFMAs of stage t sit in
+// the same straight-line block as the generation of stage t+1, so the
+// hardware overlaps matrix and vector work.  The 1-D tables of stage t+2 are
+// streamed from memory meanwhile.
 // Accumulation: the MFMAs accumulate into a fresh FP32 register block for
 // kG2Flush stages, which is then added into the running FP32 sum with
 // round-to-nearest VALU adds.  Long MFMA accumulation chains drift
@@ -62,13 +87,14 @@ __device__ __forceinline__ void split2(float a, float b, uint32_t& h, uint32_t& 
 // short chains plus rounded adds keep the Gram error unbiased.
 constexpr int kGmT = 256;                                   // tile edge of the partial layout
 constexpr int kG2H = 128;                                   // columns per work-group
-constexpr int kGmKC = 16;
 constexpr int kG2Threads = 256;
 constexpr int kG2Flush = 16;                                // stages per MFMA chain
 constexpr int kG2Slots = kGmT + kG2H;                       // 384 column slots per stage
+constexpr int kG2SlotPitch = kGmKC + 8;                     // bf16 per slot (16 samples + pad)
+constexpr int kG2TabPitch = kGmKC + 4;                      // floats per 1-D table row (16 + pad)
 constexpr int kGmChunk = 8192;                              // samples per FP32 partial
 constexpr int64_t kGmPartCap = 4ll << 30;                   // bytes of partials per pass
-constexpr int kGmStageElems = 3 * kG2Slots * kGmKC;         // bf16 per stage
+constexpr int kGmStageElems = 3 * kG2Slots * kG2SlotPitch;  // bf16 per stage buffer
 
 struct GramPlan {
   int T, ntiles, splits_total, splits_per_pass, passes;
@@ -94,61 +120,48 @@ int64_t gram_mixed_part_elems(int64_t N, int M, int* splitk_out) {
   return (int64_t)g.splits_per_pass * g.ntiles * kGmT * kGmT;
 }
 
-// 1-D tables of a 16-sample stage, FP64, layout [j*n + k][16].
-__device__ __forceinline__ void gm_fill_tab(const double* __restrict__ x, int64_t r1, int p, int n, int64_t s0,
-                                            const double* __restrict__ tab, double* __restrict__ out) {
-  const double* rc1 = tab + kTabRc1;
-  const double* rc2 = tab + kTabRc2;
-  const int t = threadIdx.x;
-  if (t < kGmKC * p) {
-    const int i = t % kGmKC, j = t / kGmKC;
-    const int64_t row = s0 + i;
-    double* o = out + (j * n) * kGmKC + i;
-    if (row < r1) {
-      const double* dc = tab + kTabDim + j * kDimStride;
-      phi_1d<double, double>(x[row * p + j], dc[0], dc[1], dc[2], rc1, rc2, n, o, kGmKC);
-    } else {
-      for (int k = 0; k < n; ++k) o[k * kGmKC] = 0.0;
-    }
-  }
-}
+// Two zero stages past the end let the kernels prefetch without bounds tests.
+int64_t gram_mixed_table_elems(int64_t N, int p, int n) { return (ceil_div(N, kGmKC) + 2) * p * n * kGmKC; }
 
-// Generate NS samples (from sample s_off of the stage) of one column and
-// store its three terms at [term][slot][s_off .. s_off+NS).
-template <int NS>
-__device__ __forceinline__ void gm_generate(const double* __restrict__ Tb, const int* off, int p, bool valid,
+// Generate NS samples (from sample s_off of the stage) of one column from
+// the stage's FP32 tables and store its three BF16 terms.
+template <int P, int NS>
+__device__ __forceinline__ void gm_generate(const float* __restrict__ Tb, const int* off, bool valid,
                                             __bf16* __restrict__ stage, int slot, int s_off) {
   float v[NS];
-  if (valid) {
-    const double2* r0 = reinterpret_cast<const double2*>(Tb + off[0] * kGmKC + s_off);
-    double d[NS];
+  {
+    const float4* r0 = reinterpret_cast<const float4*>(Tb + off[0] * kG2TabPitch + s_off);
 #pragma unroll
-    for (int q = 0; q < NS / 2; ++q) {
-      const double2 u = r0[q];
-      d[2 * q] = u.x;
-      d[2 * q + 1] = u.y;
+    for (int q = 0; q < NS / 4; ++q) {
+      const float4 u = r0[q];
+      v[4 * q] = u.x;
+      v[4 * q + 1] = u.y;
+      v[4 * q + 2] = u.z;
+      v[4 * q + 3] = u.w;
     }
-    for (int j = 1; j < p; ++j) {
-      const double2* rj = reinterpret_cast<const double2*>(Tb + off[j] * kGmKC + s_off);
+  }
 #pragma unroll
-      for (int q = 0; q < NS / 2; ++q) {
-        const double2 u = rj[q];
-        d[2 * q] *= u.x;
-        d[2 * q + 1] *= u.y;
-      }
+  for (int j = 1; j < P; ++j) {
+    const float4* rj = reinterpret_cast<const float4*>(Tb + off[j] * kG2TabPitch + s_off);
+#pragma unroll
+    for (int q = 0; q < NS / 4; ++q) {
+      const float4 u = rj[q];
+      v[4 * q] *= u.x;
+      v[4 * q + 1] *= u.y;
+      v[4 * q + 2] *= u.z;
+      v[4 * q + 3] *= u.w;
     }
-#pragma unroll
-    for (int i = 0; i < NS; ++i) v[i] = (float)d[i];
-  } else {
+  }
+  if (!valid) {
 #pragma unroll
     for (int i = 0; i < NS; ++i) v[i] = 0.0f;
   }
   uint32_t h[NS / 2], m[NS / 2], l[NS / 2];
 #pragma unroll
   for (int q = 0; q < NS / 2; ++q) split3(v[2 * q], v[2 * q + 1], h[q], m[q], l[q]);
-  uint4* dh = reinterpret_cast<uint4*>(stage + (0 * kG2Slots + slot) * kGmKC + s_off);
-  uint4* dm = reinterpret_cast<uint4*>(stage + (1 * kG2Slots + slot) * kGmKC + s_off);
-  uint4* dl = reinterpret_cast<uint4*>(stage + (2 * kG2Slots + slot) * kGmKC + s_off);
+  uint4* dh = reinterpret_cast<uint4*>(stage + (0 * kG2Slots + slot) * kG2SlotPitch + s_off);
+  uint4* dm = reinterpret_cast<uint4*>(stage + (1 * kG2Slots + slot) * kG2SlotPitch + s_off);
+  uint4* dl = reinterpret_cast<uint4*>(stage + (2 * kG2Slots + slot) * kG2SlotPitch + s_off);
 #pragma unroll
   for (int q = 0; q < NS / 8; ++q) {
     dh[q] = uint4{h[4 * q], h[4 * q + 1], h[4 * q + 2], h[4 * q + 3]};
@@ -157,16 +170,17 @@ __device__ __forceinline__ void gm_generate(const double* __restrict__ Tb, const
   }
 }
 
-__global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const double* __restrict__ x, int64_t N, int p,
-                                                                int n, int M, const double* __restrict__ tab,
-                                                                int T, int split0, float* __restrict__ part) {
+template <int P>
+__global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __restrict__ tab32, int64_t N, int n,
+                                                                int M, int T, int split0, float* __restrict__ part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smraw[];
-  __bf16* stg[2];
-  stg[0] = reinterpret_cast<__bf16*>(smraw);
-  stg[1] = stg[0] + kGmStageElems;
-  double* tb[2];
-  tb[0] = reinterpret_cast<double*>(smraw + 2 * kGmStageElems * sizeof(__bf16));
-  tb[1] = tb[0] + p * n * kGmKC;
+  // LDS: two stage buffers of split Phi, then two stage buffers of 1-D
+  // tables.  Addressed as base + offset so the compiler keeps them in LDS.
+  __bf16* const stg0 = reinterpret_cast<__bf16*>(smraw);
+  float* const tb0 = reinterpret_cast<float*>(smraw + 2 * kGmStageElems * sizeof(__bf16));
+  const int rows = P * n;                       // 1-D table rows per stage
+  const int tbs = rows * kG2TabPitch;           // floats per table buffer
+  const int tchunks = rows * (kGmKC / 4);       // float4 per stage of the table
 
   int tile = blockIdx.x >> 1, I = 0;
   const int h = blockIdx.x & 1;
@@ -179,22 +193,22 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const double* __
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wr = wv >> 1, wc = wv & 1;
 
-  // generation roles: I-block column tid (16 samples); J-half column tid/2,
-  // samples (tid&1)*8..+8 (off-diagonal tiles only)
   const int colI = I * kGmT + tid;
   const bool validI = colI < M;
   const int colJ = J * kGmT + h * kG2H + (tid >> 1);
   const bool genJ = !diag;
   const bool validJ = genJ && colJ < M;
-  int offI[GP_MAX_P], offJ[GP_MAX_P];
+  int offI[P], offJ[P];
   {
     int rem = validI ? colI : 0;
-    for (int j = p - 1; j >= 0; --j) {
+#pragma unroll
+    for (int j = P - 1; j >= 0; --j) {
       offI[j] = j * n + rem % n;
       rem /= n;
     }
     rem = validJ ? colJ : 0;
-    for (int j = p - 1; j >= 0; --j) {
+#pragma unroll
+    for (int j = P - 1; j >= 0; --j) {
       offJ[j] = j * n + rem % n;
       rem /= n;
     }
@@ -216,61 +230,92 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const double* __
   int64_t r1 = r0 + kGmChunk;
   if (r1 > N) r1 = N;
   const int nst = (int)ceil_div(r1 - r0, kGmKC);
-
-  gm_fill_tab(x, r1, p, n, r0, tab, tb[0]);
-  __syncthreads();
-  gm_generate<16>(tb[0], offI, p, validI, stg[0], tid, 0);
-  if (genJ) gm_generate<8>(tb[0], offJ, p, validJ, stg[0], kGmT + (tid >> 1), (tid & 1) * 8);
-  if (nst > 1) gm_fill_tab(x, r1, p, n, r0 + kGmKC, tab, tb[1]);
-  __syncthreads();
-
-  for (int st = 0; st < nst; ++st) {
-    const __bf16* S = stg[st & 1];
-    bf16x8 bop[2][3];
+  const int64_t st0 = r0 / kGmKC;
+  // table stage loader: thread t moves float4 number t and t + 256 (P*n <= 128
+  // rows of 16 floats = at most 512 float4).  The table carries two zero
+  // stages past the last sample, so stage st0 + st + 2 is always readable.
+  auto load_tab = [&](int64_t gst, float4* reg) {
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int u = 0; u < 2; ++u) {
+      const int q = tid + u * kG2Threads;
+      if (q < tchunks) reg[u] = reinterpret_cast<const float4*>(tab32 + gst * rows * kGmKC)[q];
+    }
+  };
+  auto store_tab = [&](float* dst, const float4* reg) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        bop[cb][q] = *reinterpret_cast<const bf16x8*>(
-            S + (q * kG2Slots + jslot + wc * 64 + cb * 32 + (lane & 31)) * kGmKC + (lane >> 5) * 8);
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      bf16x8 aop[3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q)
-        aop[q] = *reinterpret_cast<const bf16x8*>(
-            S + (q * kG2Slots + wr * 128 + rb * 32 + (lane & 31)) * kGmKC + (lane >> 5) * 8);
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        f32x16 c = acc[rb][cb];
-        c = mfma_bf16(aop[1], bop[cb][1], c);  // mid*mid
-        c = mfma_bf16(aop[2], bop[cb][0], c);  // lo*hi
-        c = mfma_bf16(aop[0], bop[cb][2], c);  // hi*lo
-        c = mfma_bf16(aop[1], bop[cb][0], c);  // mid*hi
-        c = mfma_bf16(aop[0], bop[cb][1], c);  // hi*mid
-        c = mfma_bf16(aop[0], bop[cb][0], c);  // hi*hi
-        acc[rb][cb] = c;
+    for (int u = 0; u < 2; ++u) {
+      const int q = tid + u * kG2Threads;
+      if (q < tchunks) {
+        const int row = q / (kGmKC / 4), c4 = q % (kGmKC / 4);
+        *reinterpret_cast<float4*>(dst + row * kG2TabPitch + c4 * 4) = reg[u];
       }
     }
-    if ((st + 1) % kG2Flush == 0 || st + 1 == nst) {
+  };
+  // Rows of stages past the chunk end must not enter the sum: stages st >= nst
+  // are never multiplied, and the chunk's own last stage is zero-padded by the
+  // table (samples >= N) or ends exactly at a chunk boundary (chunks are
+  // multiples of 16).
+  float4 treg[2];
+  load_tab(st0, treg);
+  store_tab(tb0, treg);
+  load_tab(st0 + 1, treg);
+  store_tab(tb0 + tbs, treg);
+  __syncthreads();
+  gm_generate<P, 16>(tb0, offI, validI, stg0, tid, 0);
+  if (genJ) gm_generate<P, 8>(tb0, offJ, validJ, stg0, kGmT + (tid >> 1), (tid & 1) * 8);
+  __syncthreads();
+
+  for (int g0 = 0; g0 < nst; g0 += kG2Flush) {
+    const int gend = min(g0 + kG2Flush, nst);
+    for (int st = g0; st < gend; ++st) {
+      // stream the tables of stage st+2 while this stage computes
+      load_tab(st0 + st + 2, treg);
+      const __bf16* S = stg0 + (st & 1) * kGmStageElems;
+      bf16x8 bop[2][3];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int q = 0; q < 3; ++q)
+          bop[cb][q] = *reinterpret_cast<const bf16x8*>(
+              S + (q * kG2Slots + jslot + wc * 64 + cb * 32 + (lane & 31)) * kG2SlotPitch + (lane >> 5) * 8);
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            sum[a][b][r] += acc[a][b][r];
-            acc[a][b][r] = 0.0f;
-          }
+      for (int rb = 0; rb < 4; ++rb) {
+        bf16x8 aop[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          aop[q] = *reinterpret_cast<const bf16x8*>(
+              S + (q * kG2Slots + wr * 128 + rb * 32 + (lane & 31)) * kG2SlotPitch + (lane >> 5) * 8);
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          f32x16 c = acc[rb][cb];
+          c = mfma_bf16(aop[1], bop[cb][1], c);  // mid*mid
+          c = mfma_bf16(aop[2], bop[cb][0], c);  // lo*hi
+          c = mfma_bf16(aop[0], bop[cb][2], c);  // hi*lo
+          c = mfma_bf16(aop[1], bop[cb][0], c);  // mid*hi
+          c = mfma_bf16(aop[0], bop[cb][1], c);  // hi*mid
+          c = mfma_bf16(aop[0], bop[cb][0], c);  // hi*hi
+          acc[rb][cb] = c;
+        }
+      }
+      // generate stage st+1 (past the chunk end this produces unused zeros)
+      {
+        __bf16* D = stg0 + ((st + 1) & 1) * kGmStageElems;
+        const float* Tn = tb0 + ((st + 1) & 1) * tbs;
+        gm_generate<P, 16>(Tn, offI, validI, D, tid, 0);
+        if (genJ) gm_generate<P, 8>(Tn, offJ, validJ, D, kGmT + (tid >> 1), (tid & 1) * 8);
+      }
+      store_tab(tb0 + (st & 1) * tbs, treg);
+      __syncthreads();
     }
-    if (st + 1 < nst) {
-      __bf16* D = stg[(st + 1) & 1];
-      const double* Tn = tb[(st + 1) & 1];
-      gm_generate<16>(Tn, offI, p, validI, D, tid, 0);
-      if (genJ) gm_generate<8>(Tn, offJ, p, validJ, D, kGmT + (tid >> 1), (tid & 1) * 8);
-    }
-    if (st + 2 < nst) gm_fill_tab(x, r1, p, n, r0 + (int64_t)(st + 2) * kGmKC, tab, tb[st & 1]);
-    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          sum[a][b][r] += acc[a][b][r];
+          acc[a][b][r] = 0.0f;
+        }
   }
 
   const int ntiles = T * (T + 1) / 2;
@@ -285,6 +330,20 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const double* __
         const int cl = h * kG2H + wc * 64 + cb * 32 + (lane & 31);
         out[row * kGmT + cl] = sum[rb][cb][r];
       }
+}
+
+typedef void (*GramKernel)(const float*, int64_t, int, int, int, int, float*);
+static GramKernel gram_kernel_for(int p) {
+  switch (p) {
+    case 1: return gram_mixed_kernel<1>;
+    case 2: return gram_mixed_kernel<2>;
+    case 3: return gram_mixed_kernel<3>;
+    case 4: return gram_mixed_kernel<4>;
+    case 5: return gram_mixed_kernel<5>;
+    case 6: return gram_mixed_kernel<6>;
+    case 7: return gram_mixed_kernel<7>;
+    default: return gram_mixed_kernel<8>;
+  }
 }
 
 // A (+)= sum of the pass's FP32 partials in split order (FP64); the first pass
@@ -305,15 +364,20 @@ __global__ void gram_mixed_reduce_kernel(const float* __restrict__ part, int spl
 }
 
 void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const double* tab, const double* reg,
-                       float* part, double* A, hipStream_t s, Prof* prof) {
+                       float* part, float* tab32, double* A, hipStream_t s, Prof* prof) {
   const GramPlan g = gram_mixed_plan(N, M);
-  const size_t lds = 2 * kGmStageElems * sizeof(__bf16) + 2 * (size_t)p * n * kGmKC * sizeof(double);
+  const int64_t nstage = ceil_div(N, kGmKC) + 2;
+  const size_t lds = 2 * kGmStageElems * sizeof(__bf16) + 2 * (size_t)p * n * kG2TabPitch * sizeof(float);
+  prof_mark(prof, GP_PH_GRAM, true, s);
+  hipLaunchKernelGGL(phi1d_table_kernel, dim3(ceil_div(nstage * p * kGmKC, 256)), dim3(256), 0, s, x, N, p, n, tab,
+                     tab32, nstage);
+  prof_mark(prof, GP_PH_GRAM, false, s);
   for (int ps = 0; ps < g.passes; ++ps) {
     const int split0 = ps * g.splits_per_pass;
     const int cnt = std::min(g.splits_per_pass, g.splits_total - split0);
     prof_mark(prof, GP_PH_GRAM, true, s);
-    hipLaunchKernelGGL(gram_mixed_kernel, dim3(2 * g.ntiles, cnt), dim3(kG2Threads), lds, s, x, N, p, n, M, tab,
-                       g.T, split0, part);
+    hipLaunchKernelGGL(gram_kernel_for(p), dim3(2 * g.ntiles, cnt), dim3(kG2Threads), lds, s, tab32, N, n, M, g.T,
+                       split0, part);
     prof_mark(prof, GP_PH_GRAM, false, s);
     prof_mark(prof, GP_PH_GRAM_REDUCE, true, s);
     hipLaunchKernelGGL(gram_mixed_reduce_kernel, dim3(ceil_div(M, 256), M), dim3(256), 0, s, part, cnt, g.T, M,
@@ -551,8 +615,11 @@ void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, con
 namespace mgp {
 hipError_t configure_kernels() {
   const int big = 160 * 1024;
-  hipError_t e = hipFuncSetAttribute((const void*)gram_mixed_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  for (int p = 1; p <= GP_MAX_P; ++p) {
+    e = hipFuncSetAttribute((const void*)gram_kernel_for(p), hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+  }
   e = hipFuncSetAttribute((const void*)predict_var_mixed_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
   return e;
 }

@@ -90,7 +90,7 @@ namespace mgp {
 gp_status fail(gp_status st, const char* fmt, ...);
 gp_status validate_params(const gp_params* prm, int64_t* M_out);
 size_t model_bytes(int64_t M, int precision);
-size_t fit_workspace_bytes(int64_t N, int64_t M, int precision);
+size_t fit_workspace_bytes(int64_t N, int p, int n, int64_t M, int precision);
 size_t predict_workspace_bytes(int64_t Ns, int64_t M, int precision);
 gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t s, gp_model** out);
 // Free a model's device memory stream-ordered on s (after a device-wide sync
