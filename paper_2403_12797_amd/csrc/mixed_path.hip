@@ -408,24 +408,36 @@ void launch_split_linv(const double* Linv, __bf16* pieces, int M, hipStream_t s)
 }
 
 // ================================================================ a5 mixed predict
-// Work-group: 128 test points x a group of 256-wide column blocks r of
-// Z = Phi_* L^-T.  8 waves in a 2 (points) x 4 (r) grid, each 64 x 64 =
-// 2 x 2 MFMA 32x32 blocks.  Per stage of 16 columns c, Phi_* (128 x 16) is
-// generated from the work-group's FP32 1-D tables and split in two terms;
-// the matching 256 x 16 slab of the L^-1 terms is copied from memory.  Squares
-// of Z are summed per point across all r of the group.  The mean partial
-// sum_c Phi_*[i][c] w[c] (FP64) is accumulated for the columns c of each
-// r-block while that block's diagonal stages are generated.
-constexpr int kPmTn = 128;
-constexpr int kPmTr = 256;
+// Z = Phi_* L^-T for a tile of TN test points x 256 columns r, over the
+// columns c <= r of L^-1 in stages of 16.  512 threads = 8 waves in a
+// WP (points) x WR (r) grid; each wave owns 64 points x 256/WR columns.
+// Per stage: every thread generates 16*TN/512 columns c of one test point
+// (lane = point, so the column digits are wave-uniform) from the work-group's
+// FP32 1-D tables, splits them in two BF16 terms into LDS; the matching slab
+// of the two L^-1 terms (256 rows x 16 columns) is prefetched into registers
+// one stage ahead.  LDS is double-buffered (one barrier per stage).  After
+// the last stage of a column block the squares of Z are summed per point.
+// The mean sum_c Phi_*[i][c] w[c] (FP64 accumulation) is formed while the
+// columns c of each column block's own diagonal stages are generated, so
+// every c is counted once.
+constexpr int kPmTR = 256;
 constexpr int kPmKC = 16;
+constexpr int kPmPitch = kPmKC + 8;     // bf16 per row of a stage buffer (pad against bank conflicts)
 constexpr int kPmThreads = 512;
-constexpr int kPmPhiElems = 2 * kPmTn * kPmKC;   // bf16 per stage (2 terms)
-constexpr int kPmLinvElems = 2 * kPmTr * kPmKC;
+
+template <int TN>
+struct PmCfg {
+  static constexpr int WP = TN / 64;               // waves along points
+  static constexpr int WR = 8 / WP;                // waves along r
+  static constexpr int CB = kPmTR / WR / 32;       // 32x32 column blocks per wave
+  static constexpr int CPT = kPmKC * TN / kPmThreads;  // columns generated per thread per stage
+  static constexpr int PHI = 2 * TN * kPmPitch;    // bf16 in one Phi_* stage buffer
+  static constexpr int LIN = 2 * kPmTR * kPmPitch; // bf16 in one L^-1 stage buffer
+};
 
 int64_t predict_mixed_part_elems(int64_t Ns, int M, int* groups_out) {
-  const int64_t ib = ceil_div(Ns, kPmTn);
-  const int64_t RB = ceil_div(M, kPmTr);
+  const int64_t ib = ceil_div(Ns, 128);
+  const int64_t RB = ceil_div(M, kPmTR);
   int64_t g = ceil_div(1024, ib);
   if (g > RB) g = RB;
   if (g < 1) g = 1;
@@ -433,144 +445,192 @@ int64_t predict_mixed_part_elems(int64_t Ns, int M, int* groups_out) {
   return 2 * g * Ns;
 }
 
+template <int TN>
 __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     const double* __restrict__ xs, int64_t Ns, int p, int n, int M, const double* __restrict__ tab,
     const __bf16* __restrict__ lpieces, const double* __restrict__ w, int rpg, double* __restrict__ part) {
+  using C = PmCfg<TN>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smraw[];
-  float* Tf = reinterpret_cast<float*>(smraw);                                   // [p*n][128]
-  __bf16* PS = reinterpret_cast<__bf16*>(smraw + (size_t)p * n * kPmTn * sizeof(float));  // [2][128][16]
-  __bf16* LS = PS + kPmPhiElems;                                                  // [2][256][16]
-  double* red = reinterpret_cast<double*>(LS + kPmLinvElems);                     // [4][128] + [4][128]
-  const int64_t i0 = (int64_t)blockIdx.x * kPmTn;
-  const int RB = (M + kPmTr - 1) / kPmTr;
+  float* const Tf = reinterpret_cast<float*>(smraw);                                  // [p*n][TN]
+  __bf16* const buf0 = reinterpret_cast<__bf16*>(smraw + (size_t)p * n * TN * sizeof(float));
+  // buffer b: Phi_* at buf0 + b*(PHI+LIN), L^-1 slab right after it
+  double* const ssw = reinterpret_cast<double*>(buf0 + 2 * (C::PHI + C::LIN));       // [WR][TN]
+  double* const mred = ssw + C::WR * TN;                                              // [512/TN][TN]
+  const int64_t i0 = (int64_t)blockIdx.x * TN;
+  const int RB = (M + kPmTR - 1) / kPmTR;
   const int rb0 = blockIdx.y * rpg, rb1 = min(rb0 + rpg, RB);
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wi = wv >> 2, wr = wv & 3;
+  const int wp = wv % C::WP, wr = wv / C::WP;
   const int P = linv_pitch(M);
   const int64_t PP = (int64_t)M * P;
 
-  {
-    const double* rc1 = tab + kTabRc1;
-    const double* rc2 = tab + kTabRc2;
-    for (int u = t; u < kPmTn * p; u += kPmThreads) {
-      const int i = u % kPmTn, j = u / kPmTn;
-      float* o = Tf + (j * n) * kPmTn + i;
-      if (i0 + i < Ns) {
-        const double* dc = tab + kTabDim + j * kDimStride;
-        phi_1d<double, float>(xs[(i0 + i) * p + j], dc[0], dc[1], dc[2], rc1, rc2, n, o, kPmTn);
-      } else {
-        for (int k = 0; k < n; ++k) o[k * kPmTn] = 0.0f;
-      }
+  for (int u = t; u < TN * p; u += kPmThreads) {
+    const int i = u % TN, j = u / TN;
+    float* o = Tf + (j * n) * TN + i;
+    if (i0 + i < Ns) {
+      const double* dc = tab + kTabDim + j * kDimStride;
+      phi_1d<double, float>(xs[(i0 + i) * p + j], dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, TN);
+    } else {
+      for (int k = 0; k < n; ++k) o[k * TN] = 0.0f;
     }
   }
-  // generation role: thread -> (point gi, 4 consecutive columns gq*4..+3)
-  const int gi = t & (kPmTn - 1), gq = t >> 7;   // gq in 0..3
-  double mean_acc = 0.0;
-  float ss[2][16];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) ss[a][r] = 0.0f;
+  for (int u = t; u < C::WR * TN; u += kPmThreads) ssw[u] = 0.0;
 
-  for (int rb = rb0; rb < rb1; ++rb) {
-    const int r0 = rb * kPmTr;
-    const int cend = min(r0 + kPmTr, M);
-    f32x16 acc[2][2];
+  // generation role: point gp, columns gq*CPT .. +CPT of each stage
+  const int gp = t % TN, gq = t / TN;
+  double mean_acc = 0.0;
+
+  // the (column block, stage) sequence of this work-group
+  auto stage_c0 = [](int k) { return k * kPmKC; };
+  auto nstages = [&](int rb) { return (int)ceil_div(min(rb * kPmTR + kPmTR, M), kPmKC); };
+
+  auto gen = [&](int rb, int k, __bf16* phi) {
+    const int c0 = stage_c0(k) + gq * C::CPT;
+    const int r0 = rb * kPmTR;
+    float v[C::CPT];
+    int prev_hi = -1;
+    float pre = 0.0f;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-    for (int c0 = 0; c0 < cend; c0 += kPmKC) {
-      __syncthreads();
-      // Phi_* stage: 4 columns for point gi
-      {
-        float v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int c = c0 + gq * 4 + u;
-          float ph = 0.0f;
-          if (c < M) {
-            int rem = c;
-            ph = 1.0f;
-            for (int j = p - 1; j >= 0; --j) {
-              ph *= Tf[(j * n + rem % n) * kPmTn + gi];
-              rem /= n;
-            }
-            if (c >= r0 && w) mean_acc = fma((double)ph, w[c], mean_acc);
+    for (int u = 0; u < C::CPT; ++u) {
+      const int c = c0 + u;
+      float ph = 0.0f;
+      if (c < M) {
+        const int hi = c / n;
+        if (hi != prev_hi) {  // wave-uniform: recompute the product over the leading dims
+          int rem = hi;
+          pre = 1.0f;
+          for (int j = p - 2; j >= 0; --j) {
+            pre *= Tf[(j * n + rem % n) * TN + gp];
+            rem /= n;
           }
-          v[u] = ph;
+          prev_hi = hi;
         }
-        uint32_t h0, l0, h1, l1;
-        split2(v[0], v[1], h0, l0);
-        split2(v[2], v[3], h1, l1);
-        *reinterpret_cast<uint2*>(PS + (0 * kPmTn + gi) * kPmKC + gq * 4) = uint2{h0, h1};
-        *reinterpret_cast<uint2*>(PS + (1 * kPmTn + gi) * kPmKC + gq * 4) = uint2{l0, l1};
+        ph = pre * Tf[((p - 1) * n + (c - hi * n)) * TN + gp];
+        if (c >= r0 && w) mean_acc = fma((double)ph, w[c], mean_acc);
       }
-      // L^-1 slab: rows r0..r0+255, columns c0..c0+15, both terms (16 B per load)
-      for (int u = t; u < 2 * kPmTr * 2; u += kPmThreads) {
-        const int q = u / (2 * kPmTr);          // term
-        const int rem = u % (2 * kPmTr);
-        const int r = rem >> 1, half = rem & 1;
-        uint4 val = uint4{0u, 0u, 0u, 0u};
-        const int row = r0 + r, c = c0 + half * 8;
-        if (row < M && c < P) val = *reinterpret_cast<const uint4*>(lpieces + q * PP + (int64_t)row * P + c);
-        *reinterpret_cast<uint4*>(LS + (q * kPmTr + r) * kPmKC + half * 8) = val;
-      }
-      __syncthreads();
-      bf16x8 aop[2][2], bop[2][2];
+      v[u] = ph;
+    }
+    uint32_t hh[C::CPT / 2], ll[C::CPT / 2];
+#pragma unroll
+    for (int q = 0; q < C::CPT / 2; ++q) split2(v[2 * q], v[2 * q + 1], hh[q], ll[q]);
+    __bf16* dh = phi + gp * kPmPitch + gq * C::CPT;
+    __bf16* dl = phi + (TN + gp) * kPmPitch + gq * C::CPT;
+    if constexpr (C::CPT == 8) {
+      *reinterpret_cast<uint4*>(dh) = uint4{hh[0], hh[1], hh[2], hh[3]};
+      *reinterpret_cast<uint4*>(dl) = uint4{ll[0], ll[1], ll[2], ll[3]};
+    } else {
+      *reinterpret_cast<uint2*>(dh) = uint2{hh[0], hh[1]};
+      *reinterpret_cast<uint2*>(dl) = uint2{ll[0], ll[1]};
+    }
+  };
+  // L^-1 slab (rows r0..r0+255, columns c0..c0+15, both terms): 1024 uint4,
+  // two per thread.  Rows past M read as zero; padding columns are zero.
+  auto lin_load = [&](int rb, int k, uint4* reg) {
+    const int c0 = stage_c0(k);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = t + u * kPmThreads;        // 0..1023
+      const int term = q >> 9, r = (q >> 1) & 255, half = q & 1;
+      const int row = rb * kPmTR + r, c = c0 + half * 8;
+      reg[u] = (row < M && c < P) ? *reinterpret_cast<const uint4*>(lpieces + term * PP + (int64_t)row * P + c)
+                                  : uint4{0u, 0u, 0u, 0u};
+    }
+  };
+  auto lin_store = [&](__bf16* lin, const uint4* reg) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = t + u * kPmThreads;
+      const int term = q >> 9, r = (q >> 1) & 255, half = q & 1;
+      *reinterpret_cast<uint4*>(lin + (term * kPmTR + r) * kPmPitch + half * 8) = reg[u];
+    }
+  };
+
+  __syncthreads();  // tables ready
+  if (rb0 < rb1) {
+    uint4 lreg[2];
+    // prologue: stage (rb0, 0) into buffer 0
+    gen(rb0, 0, buf0);
+    lin_load(rb0, 0, lreg);
+    lin_store(buf0 + C::PHI, lreg);
+    __syncthreads();
+    int b = 0;
+    for (int rb = rb0; rb < rb1; ++rb) {
+      const int ns = nstages(rb);
+      f32x16 acc[2][C::CB];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-          aop[a][q] = *reinterpret_cast<const bf16x8*>(PS + (q * kPmTn + wi * 64 + a * 32 + (lane & 31)) * kPmKC +
-                                                       (lane >> 5) * 8);
+        for (int cb = 0; cb < C::CB; ++cb)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+          for (int r = 0; r < 16; ++r) acc[a][cb][r] = 0.0f;
+      for (int k = 0; k < ns; ++k) {
+        // next stage in the sequence
+        int nrb = rb, nk = k + 1;
+        if (nk == ns) {
+          nrb = rb + 1;
+          nk = 0;
+        }
+        const bool has_next = nrb < rb1;
+        if (has_next) lin_load(nrb, nk, lreg);
+        const __bf16* PHs = buf0 + b * (C::PHI + C::LIN);
+        const __bf16* LNs = PHs + C::PHI;
+        bf16x8 aop[2][2], bop[C::CB][2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-          bop[b][q] = *reinterpret_cast<const bf16x8*>(LS + (q * kPmTr + wr * 64 + b * 32 + (lane & 31)) * kPmKC +
-                                                       (lane >> 5) * 8);
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            aop[a][q] = *reinterpret_cast<const bf16x8*>(
+                PHs + (q * TN + wp * 64 + a * 32 + (lane & 31)) * kPmPitch + (lane >> 5) * 8);
+#pragma unroll
+        for (int cb = 0; cb < C::CB; ++cb)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            bop[cb][q] = *reinterpret_cast<const bf16x8*>(
+                LNs + (q * kPmTR + wr * (kPmTR / C::WR) + cb * 32 + (lane & 31)) * kPmPitch + (lane >> 5) * 8);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int cb = 0; cb < C::CB; ++cb) acc[a][cb] = mfma_bf16(aop[a][1], bop[cb][0], acc[a][cb]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int cb = 0; cb < C::CB; ++cb) acc[a][cb] = mfma_bf16(aop[a][0], bop[cb][1], acc[a][cb]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int cb = 0; cb < C::CB; ++cb) acc[a][cb] = mfma_bf16(aop[a][0], bop[cb][0], acc[a][cb]);
+        if (has_next) {
+          __bf16* nb = buf0 + (b ^ 1) * (C::PHI + C::LIN);
+          gen(nrb, nk, nb);
+          lin_store(nb + C::PHI, lreg);
+        }
+        __syncthreads();
+        b ^= 1;
+      }
+      // squares of this column block, summed over the wave's columns
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          f32x16 c = acc[a][b];
-          c = mfma_bf16(aop[a][1], bop[b][0], c);
-          c = mfma_bf16(aop[a][0], bop[b][1], c);
-          c = mfma_bf16(aop[a][0], bop[b][0], c);
-          acc[a][b] = c;
+        for (int r = 0; r < 16; ++r) {
+          float s2 = 0.0f;
+#pragma unroll
+          for (int cb = 0; cb < C::CB; ++cb) s2 = fmaf(acc[a][cb][r], acc[a][cb][r], s2);
+          double v = (double)s2;
+          v += __shfl_xor(v, 1);
+          v += __shfl_xor(v, 2);
+          v += __shfl_xor(v, 4);
+          v += __shfl_xor(v, 8);
+          v += __shfl_xor(v, 16);
+          if ((lane & 31) == 0) ssw[wr * TN + wp * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] += v;
         }
     }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) ss[a][r] = fmaf(acc[a][b][r], acc[a][b][r], ss[a][r]);
   }
-  // reduce squares over the 32 lanes that hold one row's columns, then over wr
+  mred[gq * TN + gp] = mean_acc;
   __syncthreads();
-  double* vred = red;               // [4][128]
-  double* mred = red + 4 * kPmTn;   // [4][128]
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      double v = (double)ss[a][r];
-      v += __shfl_xor(v, 1);
-      v += __shfl_xor(v, 2);
-      v += __shfl_xor(v, 4);
-      v += __shfl_xor(v, 8);
-      v += __shfl_xor(v, 16);
-      if ((lane & 31) == 0) vred[wr * kPmTn + wi * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] = v;
-    }
-  mred[gq * kPmTn + gi] = mean_acc;
-  __syncthreads();
-  if (t < kPmTn && i0 + t < Ns) {
-    const double v = ((vred[t] + vred[kPmTn + t]) + vred[2 * kPmTn + t]) + vred[3 * kPmTn + t];
-    const double mu = ((mred[t] + mred[kPmTn + t]) + mred[2 * kPmTn + t]) + mred[3 * kPmTn + t];
+  if (t < TN && i0 + t < Ns) {
+    double v = 0.0, mu = 0.0;
+    for (int q = 0; q < C::WR; ++q) v += ssw[q * TN + t];
+    for (int q = 0; q < kPmThreads / TN; ++q) mu += mred[q * TN + t];
     part[(int64_t)blockIdx.y * 2 * Ns + i0 + t] = v;
     part[(int64_t)blockIdx.y * 2 * Ns + Ns + i0 + t] = mu;
   }
@@ -589,26 +649,44 @@ __global__ void predict_mixed_reduce_kernel(const double* __restrict__ part, int
   if (mean) mean[i] = mu;
 }
 
+template <int TN>
+static size_t predict_lds_bytes(int p, int n) {
+  using C = PmCfg<TN>;
+  return (size_t)p * n * TN * sizeof(float) + 2 * (C::PHI + C::LIN) * sizeof(__bf16) +
+         (size_t)(C::WR + kPmThreads / TN) * TN * sizeof(double);
+}
+
+// TN = 256 test points per work-group when its FP32 1-D tables fit, else 128.
+static int predict_tn(int p, int n) { return predict_lds_bytes<256>(p, n) <= 160 * 1024 ? 256 : 128; }
+
 void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, const double* tab,
                           const __bf16* linv_pieces, const double* w, double sigma2, double* part, double* mean,
                           double* var, hipStream_t s, Prof* prof) {
   if (Ns <= 0) return;
+  const int TN = predict_tn(p, n);
+  const int64_t ib = ceil_div(Ns, TN);
+  const int RB = (int)ceil_div(M, kPmTR);
   int groups = 1;
-  predict_mixed_part_elems(Ns, M, &groups);
-  const int RB = (int)ceil_div(M, kPmTr);
-  const int rpg = (int)ceil_div(RB, groups);
+  predict_mixed_part_elems(Ns, M, &groups);   // upper bound of the partial buffer
+  int want = (int)ceil_div(1024, ib);
+  if (want > groups) want = groups;
+  if (want < 1) want = 1;
+  const int rpg = (int)ceil_div(RB, want);
   groups = (int)ceil_div(RB, rpg);
-  const size_t lds = (size_t)p * n * kPmTn * sizeof(float) + (kPmPhiElems + kPmLinvElems) * sizeof(__bf16) +
-                     8 * kPmTn * sizeof(double);
   prof_mark(prof, GP_PH_PREDICT, true, s);
-  hipLaunchKernelGGL(predict_var_mixed_kernel, dim3(ceil_div(Ns, kPmTn), groups), dim3(kPmThreads), lds, s, xs, Ns,
-                     p, n, M, tab, linv_pieces, w, rpg, part);
+  if (TN == 256)
+    hipLaunchKernelGGL(predict_var_mixed_kernel<256>, dim3(ib, groups), dim3(kPmThreads), predict_lds_bytes<256>(p, n),
+                       s, xs, Ns, p, n, M, tab, linv_pieces, w, rpg, part);
+  else
+    hipLaunchKernelGGL(predict_var_mixed_kernel<128>, dim3(ib, groups), dim3(kPmThreads), predict_lds_bytes<128>(p, n),
+                       s, xs, Ns, p, n, M, tab, linv_pieces, w, rpg, part);
   prof_mark(prof, GP_PH_PREDICT, false, s);
   prof_mark(prof, GP_PH_PREDICT_REDUCE, true, s);
   hipLaunchKernelGGL(predict_mixed_reduce_kernel, dim3(ceil_div(Ns, 256)), dim3(256), 0, s, part, groups, Ns,
                      sigma2, mean, var);
   prof_mark(prof, GP_PH_PREDICT_REDUCE, false, s);
 }
+
 
 }  // namespace mgp
 
@@ -620,7 +698,9 @@ hipError_t configure_kernels() {
     e = hipFuncSetAttribute((const void*)gram_kernel_for(p), hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
   }
-  e = hipFuncSetAttribute((const void*)predict_var_mixed_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  e = hipFuncSetAttribute((const void*)predict_var_mixed_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)predict_var_mixed_kernel<128>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
   return e;
 }
 }  // namespace mgp

@@ -1,0 +1,60 @@
+"""Full-size parity at the c3 workload (p = 4, n = 8, M = 4096, N = N_* = 1e6)
+in the configuration bench.py times: the GPU fit on all 1e6 training points
+and the prediction of all 1e6 test points, checked at 2000 seeded test points
+against the FP64 oracle's values stored in tests/golden/c3_oracle.npz (written
+by tests/golden/make_c3_golden.py, which calls only the oracle).
+
+Tolerances (normwise relative over the sample): mixed 1e-5 mean / 1e-4
+variance; FP64 1e-10.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2403_12797_amd import binding as B
+from paper_2403_12797_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_oracle.npz")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    g = np.load(GOLDEN)
+    P = wl.config("c3")
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (P.x, P.y, P.xs)]
+    ctx = B.Context(0)
+    yield torch, P, dev, g, ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision,tm,tv,tw", [(B.PREC_MIXED, 1e-5, 1e-4, None), (B.PREC_FP64, 1e-10, 1e-10, 1e-10)])
+def test_c3_full_size(setup, precision, tm, tv, tw):
+    torch, P, (x, y, xs), g, ctx = setup
+    print(f"[case] c3 full N={P.N} Ns={P.Ns} precision={precision}", flush=True)
+    m = ctx.fit(x, y, p=P.p, n=P.n, sigma=P.sigma, eps=P.eps, alpha=P.alpha, precision=precision)
+    mean = torch.empty(P.Ns, dtype=torch.float64, device="cuda")
+    var = torch.empty_like(mean)
+    ctx.predict(m, xs, mean, var)
+    torch.cuda.synchronize()
+    idx = g["idx"]
+    gm, gv = mean.cpu().numpy()[idx], var.cpu().numpy()[idx]
+    em, ev = rel(gm, g["mean"]), rel(gv, g["var"])
+    w = m.get(B.MODEL_W)
+    ew = rel(w, g["w"])
+    eb = rel(m.get(B.MODEL_B), g["b"])
+    print(f"[err] c3 full precision={precision}: mean {em:.3e} var {ev:.3e} w {ew:.3e} b {eb:.3e}", flush=True)
+    assert np.all(np.isfinite(mean.cpu().numpy())) and np.all(var.cpu().numpy() > 0)
+    assert em <= tm and ev <= tv
+    assert eb <= 1e-12
+    if tw is not None:
+        assert ew <= tw
+    m.free()

@@ -1,0 +1,152 @@
+"""Served path (gp_submit / gp_poll): results equal the synchronous calls,
+each result is the same alone and in a mix of concurrently admitted requests,
+admission respects the HBM budget, and an injected failure stays with its
+request."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2403_12797_amd import binding as B
+from paper_2403_12797_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def problems():
+    # uneven N, p, n (a small served mix)
+    shapes = [(2, 6, 3000, 500), (3, 6, 20000, 2000), (4, 6, 8000, 1000), (5, 4, 12000, 300),
+              (2, 12, 50000, 4000), (3, 5, 1000, 100), (4, 5, 30000, 2500), (1, 20, 7000, 700)]
+    return [wl.random_problem(100 + i, p, n, N, Ns) for i, (p, n, N, Ns) in enumerate(shapes)]
+
+
+def submit(ctx, torch, P, prec, keep):
+    x, y, xs = dev(torch, P.x), dev(torch, P.y), dev(torch, P.xs)
+    mean = torch.full((P.Ns,), float("nan"), dtype=torch.float64, device="cuda")
+    var = torch.full((P.Ns,), float("nan"), dtype=torch.float64, device="cuda")
+    prm = B.make_params(P.p, P.n, P.sigma, P.eps, P.alpha, prec)
+    rid = ctx.submit(B.REQ_FIT_PREDICT, x=x, y=y, params=prm, xs=xs, mean=mean, var=var)
+    keep.append((x, y, xs, prm))
+    return rid, mean, var
+
+
+def sync_result(ctx, torch, P, prec):
+    x, y, xs = dev(torch, P.x), dev(torch, P.y), dev(torch, P.xs)
+    m = ctx.fit(x, y, p=P.p, n=P.n, sigma=P.sigma, eps=P.eps, alpha=P.alpha, precision=prec)
+    mean = torch.empty(P.Ns, dtype=torch.float64, device="cuda")
+    var = torch.empty_like(mean)
+    ctx.predict(m, xs, mean, var)
+    torch.cuda.synchronize()
+    m.free()
+    return mean.cpu().numpy(), var.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [B.PREC_MIXED, B.PREC_FP64])
+def test_alone_equals_mix_equals_sync(torch_cuda, prec):
+    torch = torch_cuda
+    Ps = problems()
+    with B.Context(0) as ctx:
+        ref = [sync_result(ctx, torch, P, prec) for P in Ps]
+        # alone: one request at a time
+        alone = []
+        keep = []
+        for P in Ps:
+            rid, mean, var = submit(ctx, torch, P, prec, keep)
+            st, _ = ctx.poll(rid, wait_us=-1)
+            assert st == B.GP_OK
+            alone.append((mean.cpu().numpy(), var.cpu().numpy()))
+        # mix: all submitted at once, polled in reverse order
+        ids = [submit(ctx, torch, P, prec, keep) for P in Ps]
+        out = [None] * len(Ps)
+        for k in reversed(range(len(Ps))):
+            st, _ = ctx.poll(ids[k][0], wait_us=-1)
+            assert st == B.GP_OK
+            out[k] = (ids[k][1].cpu().numpy(), ids[k][2].cpu().numpy())
+        # a retired id is gone
+        with pytest.raises(B.GpError) as ei:
+            ctx.poll(ids[0][0], wait_us=0)
+        assert ei.value.status == B.GP_ENOTFOUND
+    for k, P in enumerate(Ps):
+        print(f"[case] served {P.name} prec={prec}", flush=True)
+        assert np.array_equal(alone[k][0], ref[k][0]) and np.array_equal(alone[k][1], ref[k][1])
+        assert np.array_equal(out[k][0], ref[k][0]) and np.array_equal(out[k][1], ref[k][1])
+
+
+def test_fit_then_predict_requests(torch_cuda):
+    torch = torch_cuda
+    P = wl.random_problem(7, 3, 6, 10000, 1500)
+    with B.Context(0) as ctx:
+        ref = sync_result(ctx, torch, P, B.PREC_MIXED)
+        x, y, xs = dev(torch, P.x), dev(torch, P.y), dev(torch, P.xs)
+        prm = B.make_params(P.p, P.n, P.sigma, P.eps, P.alpha, B.PREC_MIXED)
+        rid = ctx.submit(B.REQ_FIT, x=x, y=y, params=prm)
+        st, model = ctx.poll(rid, wait_us=-1, want_model=True)
+        assert st == B.GP_OK and model is not None
+        # the model stays device-resident and serves several predicts
+        for _ in range(3):
+            mean = torch.empty(P.Ns, dtype=torch.float64, device="cuda")
+            var = torch.empty_like(mean)
+            rid = ctx.submit(B.REQ_PREDICT, model=model, xs=xs, mean=mean, var=var)
+            st, _ = ctx.poll(rid, wait_us=-1)
+            assert st == B.GP_OK
+            assert np.array_equal(mean.cpu().numpy(), ref[0]) and np.array_equal(var.cpu().numpy(), ref[1])
+        model.free()
+
+
+def test_admission_by_budget(torch_cuda):
+    torch = torch_cuda
+    Ps = problems()[:4]
+    keep = []
+    # a budget that fits one request at a time: all still complete, in order
+    with B.Context(0, hbm_budget_bytes=64 << 20) as ctx:
+        ids = [submit(ctx, torch, P, B.PREC_MIXED, keep) for P in Ps]
+        for rid, mean, var in ids:
+            st, _ = ctx.poll(rid, wait_us=-1)
+            assert st == B.GP_OK
+            assert np.all(np.isfinite(mean.cpu().numpy()))
+    # a request larger than the whole budget is refused at submit
+    with B.Context(0, hbm_budget_bytes=1 << 20) as ctx:
+        with pytest.raises(B.GpError) as ei:
+            submit(ctx, torch, Ps[1], B.PREC_MIXED, keep)
+        assert ei.value.status == B.GP_ENOMEM
+
+
+def test_injected_cholesky_failure_stays_with_its_request(torch_cuda, monkeypatch):
+    torch = torch_cuda
+    Ps = problems()[:3]
+    keep = []
+    monkeypatch.setenv("MGP_FAULT", "chol")
+    with B.Context(0) as ctx:
+        ids = [submit(ctx, torch, P, B.PREC_MIXED, keep) for P in Ps]
+        with pytest.raises(B.GpError) as ei:
+            ctx.poll(ids[0][0], wait_us=-1)
+        assert ei.value.status == B.GP_ENOTSPD
+        for rid, mean, var in ids[1:]:
+            st, _ = ctx.poll(rid, wait_us=-1)
+            assert st == B.GP_OK
+
+
+def test_submit_validation(torch_cuda):
+    torch = torch_cuda
+    with B.Context(0) as ctx:
+        x = torch.zeros((10, 2), dtype=torch.float64, device="cuda")
+        y = torch.zeros(10, dtype=torch.float64, device="cuda")
+        with pytest.raises(B.GpError) as ei:
+            ctx.submit(B.REQ_FIT, x=x, y=y, params=B.make_params(2, 0, 0.1, 1.0, 1.0))
+        assert ei.value.status == B.GP_EINVAL
+        with pytest.raises(B.GpError):
+            ctx.submit(B.REQ_PREDICT, xs=x)
+        with pytest.raises(B.GpError):
+            ctx.submit(7, x=x, y=y, params=B.make_params(2, 3, 0.1, 1.0, 1.0))
