@@ -68,8 +68,8 @@ size_t fit_workspace_bytes(int64_t N, int p, int n, int64_t M, int precision) {
                                               (size_t)gram_mixed_table_elems(N, p, n) * 4 + 256
                                         : (size_t)gram_f64_part_elems(N, (int)M, nullptr) * 8;
   size_t v = (size_t)phiT_part_elems(N, (int)M) * 8 + (size_t)N * 8 + 4 * (size_t)M * 8 +
-             (size_t)ceil_div(M, 256) * M * 8;
-  return g + v + 1024;
+             (size_t)ceil_div(M, 256) * M * 8 + trtri_workspace_elems((int)M) * 8;
+  return g + v + 2048;
 }
 
 size_t predict_workspace_bytes(int64_t Ns, int64_t M, int precision) {
@@ -188,6 +188,7 @@ void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void*
   double* r = (double*)take((size_t)M * 8);
   double* d = (double*)take((size_t)M * 8);
   double* ltpart = (double*)take((size_t)ceil_div(M, 256) * M * 8);
+  double* trws = (double*)take(trtri_workspace_elems(M) * 8);
 
   Prof* pr = &m->ctx->prof;
   hipMemsetAsync(m->flags, 0, 64, s);
@@ -208,7 +209,7 @@ void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void*
   launch_cholesky(m->L, M, m->Dinv, m->flags, s);
   prof_mark(pr, GP_PH_CHOL, false, s);
   prof_mark(pr, GP_PH_TRTRI, true, s);
-  launch_trtri(m->L, m->Dinv, m->Linv, M, m->flags, s);
+  launch_trtri(m->L, m->Dinv, m->Linv, trws, M, m->flags, s);
   prof_mark(pr, GP_PH_TRTRI, false, s);
   prof_mark(pr, GP_PH_SOLVE, true, s);
   launch_lower_matvec(m->Linv, m->b, z, M, s);

@@ -189,15 +189,21 @@ constexpr int kNbLd = kNb + 1;
 
 __global__ void __launch_bounds__(256) potrf_diag_kernel(double* __restrict__ A, int M, int k0,
                                                          double* __restrict__ Dinv, int* __restrict__ info) {
+  // Factor the diagonal block B = L L^T and form X = L^-1 in the same sweep:
+  // step j takes the pivot, scales column j of L and row j of X
+  // (X[j][:] = R[j][:] / L[j][j]), then updates the trailing block of B and
+  // the rows R[i][:] = e_i - sum_{q<j} L[i][q] X[q][:] of the rows below.
+  // Thread t owns row t/4 and every fourth column starting at t%4.
   __shared__ double a[kNb * kNbLd];
-  __shared__ double inv[kNb * kNbLd];
+  __shared__ double x[kNb * kNbLd];
   __shared__ int bad;
   if (*info) return;
   const int t = threadIdx.x;
   const int nb = min(kNb, M - k0);
-  for (int idx = t; idx < kNb * kNb; idx += 256) {
-    const int i = idx / kNb, c = idx % kNb;
-    a[i * kNbLd + c] = (i < nb && c < nb && c <= i) ? A[(int64_t)(k0 + i) * M + k0 + c] : 0.0;
+  const int ri = t >> 2, c0 = t & 3;
+  for (int c = c0; c < kNb; c += 4) {
+    a[ri * kNbLd + c] = (ri < nb && c < nb && c <= ri) ? A[(int64_t)(k0 + ri) * M + k0 + c] : 0.0;
+    x[ri * kNbLd + c] = (ri == c) ? 1.0 : 0.0;
   }
   if (t == 0) bad = 0;
   __syncthreads();
@@ -212,12 +218,15 @@ __global__ void __launch_bounds__(256) potrf_diag_kernel(double* __restrict__ A,
     __syncthreads();
     if (bad) break;
     const double piv = a[j * kNbLd + j];
-    for (int i = j + 1 + t; i < nb; i += 256) a[i * kNbLd + j] /= piv;
+    const double rp = 1.0 / piv;
+    if (ri > j && ri < nb && c0 == 0) a[ri * kNbLd + j] *= rp;
+    if (ri == j)
+      for (int c = c0; c <= j; c += 4) x[j * kNbLd + c] *= rp;
     __syncthreads();
-    const int w = nb - j - 1;
-    for (int idx = t; idx < w * w; idx += 256) {
-      const int i = j + 1 + idx / w, c = j + 1 + idx % w;
-      if (c <= i) a[i * kNbLd + c] -= a[i * kNbLd + j] * a[c * kNbLd + j];
+    if (ri > j && ri < nb) {
+      const double lij = a[ri * kNbLd + j];
+      for (int c = j + 1 + c0; c <= ri; c += 4) a[ri * kNbLd + c] -= lij * a[c * kNbLd + j];
+      for (int c = c0; c <= j; c += 4) x[ri * kNbLd + c] -= lij * x[j * kNbLd + c];
     }
     __syncthreads();
   }
@@ -225,25 +234,10 @@ __global__ void __launch_bounds__(256) potrf_diag_kernel(double* __restrict__ A,
     if (t == 0) *info = bad;
     return;
   }
-  // inverse of the lower-triangular block, one column per thread
-  if (t < kNb) {
-    const int c = t;
-    for (int i = 0; i < kNb; ++i) inv[i * kNbLd + c] = 0.0;
-    if (c < nb) {
-      inv[c * kNbLd + c] = 1.0 / a[c * kNbLd + c];
-      for (int i = c + 1; i < nb; ++i) {
-        double s = 0.0;
-        for (int q = c; q < i; ++q) s = fma(a[i * kNbLd + q], inv[q * kNbLd + c], s);
-        inv[i * kNbLd + c] = -s / a[i * kNbLd + i];
-      }
-    }
-  }
-  __syncthreads();
   double* D = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
-  for (int idx = t; idx < kNb * kNb; idx += 256) {
-    const int i = idx / kNb, c = idx % kNb;
-    D[idx] = inv[i * kNbLd + c];
-    if (i < nb && c < nb) A[(int64_t)(k0 + i) * M + k0 + c] = (c <= i) ? a[i * kNbLd + c] : 0.0;
+  for (int c = c0; c < kNb; c += 4) {
+    D[ri * kNb + c] = (ri < nb && c < nb && c <= ri) ? x[ri * kNbLd + c] : 0.0;
+    if (ri < nb && c < nb) A[(int64_t)(k0 + ri) * M + k0 + c] = (c <= ri) ? a[ri * kNbLd + c] : 0.0;
   }
 }
 
@@ -339,50 +333,48 @@ void launch_cholesky(double* A, int M, double* Dinv, int* info, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- L^-1
-// Block row ib of X = L^-1:  X_ib,cb = -Dinv_ib * sum_{q=cb}^{ib-1} L_ib,q X_q,cb,
-// X_ib,ib = Dinv_ib.  One work-group per block column cb <= ib.
-__global__ void __launch_bounds__(256) trtri_row_kernel(const double* __restrict__ L,
-                                                        const double* __restrict__ Dinv,
-                                                        double* __restrict__ X, int M, int ib,
-                                                        const int* __restrict__ info) {
-  __shared__ double Ls[kNb * kNbLd];
-  __shared__ double Xs[kNb * kNbLd];
-  if (*info) return;
-  const int cb = blockIdx.x;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int R0 = ib * kNb, C0 = cb * kNb;
-  const double* Di = Dinv + (int64_t)ib * kNb * kNb;
-  if (cb == ib) {
-    for (int idx = t; idx < kNb * kNb; idx += 256) {
-      const int i = idx / kNb, c = idx % kNb;
-      if (R0 + i < M && C0 + c < M) X[(int64_t)(R0 + i) * M + C0 + c] = Di[idx];
-    }
-    return;
+// Bottom-up recursive inversion.  The diagonal 64-blocks of X = L^-1 are the
+// inverses formed during the factorisation.  Level l merges pairs of
+// diagonal blocks of width b = 64*2^l: for the pair starting at row o,
+//   X21 = -X22 (L21 X11),  L21 = L[o+b.., o..o+b), X11, X22 its diagonal blocks,
+// as two batched FP64-MFMA GEMMs over all pairs of the level (T holds L21 X11).
+// Triangularity skips zero products: X11 is lower (k >= n), X22 is lower
+// (k <= m).  Rows and columns past M are zero.
+__global__ void trtri_diag_kernel(const double* __restrict__ Dinv, double* __restrict__ X, int M) {
+  const int blk = blockIdx.x;
+  const int o = blk * kNb;
+  for (int idx = threadIdx.x; idx < kNb * kNb; idx += blockDim.x) {
+    const int i = idx / kNb, c = idx % kNb;
+    if (o + i < M && o + c < M) X[(int64_t)(o + i) * M + o + c] = Dinv[(int64_t)blk * kNb * kNb + idx];
   }
+}
+
+// One 64x64 output tile of C = sum_k A[m][k] B[k][n] with A, B row-major in
+// global memory (lda, ldb), k in [kb, ke), rows m >= mv / columns n >= nv and
+// k >= kv read as zero.  4 waves, each a 32x32 quarter (2x2 MFMA blocks).
+__device__ __forceinline__ void tile_gemm64(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+                                            int64_t ldb, int kb, int ke, int mv, int nv, int kv, double* As,
+                                            double* Bs, f64x4 (&acc)[2][2]) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wr = wv >> 1, wc = wv & 1;
-  f64x4 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // Y = sum_q L[R-block][q-block] * X[q-block][C-block]
-  for (int qb = cb; qb < ib; ++qb) {
-    const int Q0 = qb * kNb;
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     __syncthreads();
-    for (int idx = t; idx < kNb * kNb; idx += 256) {
-      const int i = idx / kNb, c = idx % kNb;
-      Ls[i * kNbLd + c] = (R0 + i < M) ? L[(int64_t)(R0 + i) * M + Q0 + c] : 0.0;
-      Xs[i * kNbLd + c] = X[(int64_t)(Q0 + i) * M + C0 + c];  // rows Q0+i < R0 <= M-1
+    // A tile 64 x 16 -> As[m][k] (pitch 17), B tile 16 x 64 -> Bs[k][n] (pitch 66)
+    for (int u = t; u < 64 * 16; u += 256) {
+      const int m = u >> 4, k = u & 15;
+      As[m * 17 + k] = (m < mv && k0 + k < kv && k0 + k < ke) ? A[(int64_t)m * lda + k0 + k] : 0.0;
+      const int kk = u >> 6, nn = u & 63;
+      Bs[kk * 66 + nn] = (nn < nv && k0 + kk < kv && k0 + kk < ke) ? B[(int64_t)(k0 + kk) * ldb + nn] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kNb / 4; ++kk) {
+    for (int kk = 0; kk < 4; ++kk) {
       const int k = kk * 4 + (lane >> 4);
       double av[2], bv[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        av[q] = Ls[(wr * 32 + q * 16 + (lane & 15)) * kNbLd + k];
-        bv[q] = Xs[k * kNbLd + wc * 32 + q * 16 + (lane & 15)];
+        av[q] = As[(wr * 32 + q * 16 + (lane & 15)) * 17 + k];
+        bv[q] = Bs[k * 66 + wc * 32 + q * 16 + (lane & 15)];
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -390,52 +382,100 @@ __global__ void __launch_bounds__(256) trtri_row_kernel(const double* __restrict
         for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
     }
   }
-  // Y -> Xs, then X_ib,cb = -Dinv_ib * Y  (Dinv in Ls)
-  __syncthreads();
+}
+
+// T[g] = L21 X11 for pair g of width b (T is b x b, row-major, per pair).
+__global__ void __launch_bounds__(256) trtri_merge_t_kernel(const double* __restrict__ L,
+                                                            const double* __restrict__ X, double* __restrict__ T,
+                                                            int M, int b, const int* __restrict__ info) {
+  __shared__ double As[64 * 17];
+  __shared__ double Bs[16 * 66];
+  if (*info) return;
+  const int g = blockIdx.z;
+  const int o = 2 * g * b;          // first row/column of the pair
+  const int r0 = o + b;             // first row of L21 / X22
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  if (r0 >= M) return;
+  const int mrows = min(b, M - r0);
+  f64x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        Xs[(wr * 32 + a * 16 + 4 * q + (lane >> 4)) * kNbLd + wc * 32 + b * 16 + (lane & 15)] = acc[a][b][q];
-  for (int idx = t; idx < kNb * kNb; idx += 256) Ls[(idx / kNb) * kNbLd + idx % kNb] = Di[idx];
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int kk = 0; kk < kNb / 4; ++kk) {
-    const int k = kk * 4 + (lane >> 4);
-    double av[2], bv[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      av[q] = Ls[(wr * 32 + q * 16 + (lane & 15)) * kNbLd + k];
-      bv[q] = Xs[k * kNbLd + wc * 32 + q * 16 + (lane & 15)];
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
+    for (int c = 0; c < 2; ++c) acc[a][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+  if (m0 < mrows) {
+    // k runs over the columns of L21 = rows of X11; X11 lower: k >= n0
+    tile_gemm64(L + (int64_t)(r0 + m0) * M + o, M, X + (int64_t)o * M + o + n0, M, n0 & ~15, b, mrows - m0, b - n0,
+                b, As, Bs, acc);
   }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wr = wv >> 1, wc = wv & 1;
+  double* Tg = T + (int64_t)g * b * b;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = R0 + wr * 32 + a * 16 + 4 * q + (lane >> 4);
-        const int col = C0 + wc * 32 + b * 16 + (lane & 15);
-        if (row < M) X[(int64_t)row * M + col] = -acc[a][b][q];
+        const int m = m0 + wr * 32 + a * 16 + 4 * q + (lane >> 4);
+        const int n = n0 + wc * 32 + c * 16 + (lane & 15);
+        if (m < b && n < b) Tg[(int64_t)m * b + n] = acc[a][c][q];
       }
 }
 
-void launch_trtri(const double* L, const double* Dinv, double* Linv, int M, const int* info, hipStream_t s) {
+// X21 = -X22 T[g].
+__global__ void __launch_bounds__(256) trtri_merge_x_kernel(double* __restrict__ X, const double* __restrict__ T,
+                                                            int M, int b, const int* __restrict__ info) {
+  __shared__ double As[64 * 17];
+  __shared__ double Bs[16 * 66];
+  if (*info) return;
+  const int g = blockIdx.z;
+  const int o = 2 * g * b;
+  const int r0 = o + b;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  if (r0 >= M) return;
+  const int mrows = min(b, M - r0);
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+  if (m0 < mrows) {
+    // X22 lower: k <= m, so k < m0 + 64
+    tile_gemm64(X + (int64_t)(r0 + m0) * M + r0, M, T + (int64_t)g * b * b + n0, b, 0, min(m0 + 64, mrows),
+                mrows - m0, b - n0, mrows, As, Bs, acc);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wr = wv >> 1, wc = wv & 1;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wr * 32 + a * 16 + 4 * q + (lane >> 4);
+        const int n = n0 + wc * 32 + c * 16 + (lane & 15);
+        if (m < mrows && n < b) X[(int64_t)(r0 + m) * M + o + n] = -acc[a][c][q];
+      }
+}
+
+size_t trtri_workspace_elems(int M) {
+  size_t mx = 64 * 64;
+  for (int b = kNb; b < M; b *= 2) {
+    const size_t need = (size_t)ceil_div(M, 2 * b) * b * b;
+    if (need > mx) mx = need;
+  }
+  return mx;
+}
+
+void launch_trtri(const double* L, const double* Dinv, double* Linv, double* ws, int M, const int* info,
+                  hipStream_t s) {
   hipMemsetAsync(Linv, 0, (size_t)M * M * sizeof(double), s);
-  const int T = (int)ceil_div(M, kNb);
-  for (int ib = 0; ib < T; ++ib)
-    hipLaunchKernelGGL(trtri_row_kernel, dim3(ib + 1), dim3(256), 0, s, L, Dinv, Linv, M, ib, info);
+  const int nblk = (int)ceil_div(M, kNb);
+  hipLaunchKernelGGL(trtri_diag_kernel, dim3(nblk), dim3(256), 0, s, Dinv, Linv, M);
+  for (int b = kNb; b < M; b *= 2) {
+    const int pairs = (int)ceil_div(M, 2 * b);
+    const int tiles = (int)ceil_div(b, 64);
+    hipLaunchKernelGGL(trtri_merge_t_kernel, dim3(tiles, tiles, pairs), dim3(256), 0, s, L, Linv, ws, M, b, info);
+    hipLaunchKernelGGL(trtri_merge_x_kernel, dim3(tiles, tiles, pairs), dim3(256), 0, s, Linv, ws, M, b, info);
+  }
 }
 
 // ---------------------------------------------------------------- triangular mat-vecs

@@ -45,9 +45,11 @@ void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const do
 // info (device int, 0 = ok, else failing column + 1).
 constexpr int kCholNb = 64;
 void launch_cholesky(double* A, int M, double* Dinv, int* info, hipStream_t s);
-// L^-1 (lower, upper part zero) from L and Dinv.
-void launch_trtri(const double* L, const double* Dinv, double* Linv, int M, const int* info,
-                  hipStream_t s);
+// L^-1 (lower, upper part zero) from L and Dinv; ws holds
+// trtri_workspace_elems(M) doubles.
+size_t trtri_workspace_elems(int M);
+void launch_trtri(const double* L, const double* Dinv, double* Linv, double* ws, int M,
+                  const int* info, hipStream_t s);
 // z = Linv b ; w = Linv^T z  (both through `tmp`, M doubles)
 void launch_lower_matvec(const double* Linv, const double* b, double* z, int M, hipStream_t s);
 void launch_lower_t_matvec(const double* Linv, const double* z, double* w, double* part, int M,

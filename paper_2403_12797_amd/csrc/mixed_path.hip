@@ -69,17 +69,19 @@ __global__ void phi1d_table_kernel(const double* __restrict__ x, int64_t N, int 
 }
 
 // Gram work-group: rows I*256..+256 and columns J*256 + h*128..+128 (half h
-// of the J-block) of Phi^T Phi, I <= J, over one chunk of samples.  256
-// threads = 4 waves in a 2 (rows) x 2 (cols) grid, each owning 128 x 64
-// outputs = 4 x 2 MFMA 32x32 blocks.
-// Stage = 16 samples.  Per stage every thread generates one I-block column
-// for the 16 samples and (off-diagonal tiles) half of one J-half column: the
-// product of the P FP32 1-D table values, split into three BF16 terms and
-// stored in LDS as [term][column slot][16 samples] (slot pitch padded against
-// bank conflicts).  LDS is double-buffered and the MFMAs of stage t sit in
-// the same straight-line block as the generation of stage t+1, so the
-// hardware overlaps matrix and vector work.  The 1-D tables of stage t+2 are
-// streamed from memory meanwhile.
+// of the J-block) of Phi^T Phi, I <= J, over one chunk of samples.  512
+// threads = 8 waves in a 4 (rows) x 2 (cols) grid, each owning 64 x 64
+// outputs = 2 x 2 MFMA 32x32 blocks (two waves per SIMD).
+// Stage = 16 samples.  A column c = hi*n + k (k its last digit) has
+// Phi[i, c] = PRE[hi][i] * phi_{p-1,k}(x_i), where PRE is the product of the
+// leading p-1 factors.  Per stage the work-group forms PRE once per column
+// prefix it needs, then every thread generates 8 samples of one I-block
+// column and 4 samples of one J-half column with one multiply each, splits
+// them into three BF16 terms and stores them in LDS as
+// [term][column slot][16 samples] (slot pitch padded against bank
+// conflicts).  Pipeline (one barrier per stage): while the MFMAs of stage t
+// run, the work-group generates stage t+1, forms PRE of stage t+2 and
+// streams the 1-D tables of stage t+3 from memory.
 // Accumulation: the MFMAs accumulate into a fresh FP32 register block for
 // kG2Flush stages, which is then added into the running FP32 sum with
 // round-to-nearest VALU adds.  Long MFMA accumulation chains drift
@@ -87,11 +89,11 @@ __global__ void phi1d_table_kernel(const double* __restrict__ x, int64_t N, int 
 // short chains plus rounded adds keep the Gram error unbiased.
 constexpr int kGmT = 256;                                   // tile edge of the partial layout
 constexpr int kG2H = 128;                                   // columns per work-group
-constexpr int kG2Threads = 256;
+constexpr int kG2Threads = 512;
 constexpr int kG2Flush = 16;                                // stages per MFMA chain
 constexpr int kG2Slots = kGmT + kG2H;                       // 384 column slots per stage
 constexpr int kG2SlotPitch = kGmKC + 8;                     // bf16 per slot (16 samples + pad)
-constexpr int kG2TabPitch = kGmKC + 4;                      // floats per 1-D table row (16 + pad)
+constexpr int kG2TabPitch = kGmKC + 4;                      // floats per table / prefix row (16 + pad)
 constexpr int kGmChunk = 8192;                              // samples per FP32 partial
 constexpr int64_t kGmPartCap = 4ll << 30;                   // bytes of partials per pass
 constexpr int kGmStageElems = 3 * kG2Slots * kG2SlotPitch;  // bf16 per stage buffer
@@ -120,66 +122,51 @@ int64_t gram_mixed_part_elems(int64_t N, int M, int* splitk_out) {
   return (int64_t)g.splits_per_pass * g.ntiles * kGmT * kGmT;
 }
 
-// Two zero stages past the end let the kernels prefetch without bounds tests.
-int64_t gram_mixed_table_elems(int64_t N, int p, int n) { return (ceil_div(N, kGmKC) + 2) * p * n * kGmKC; }
+// Three zero stages past the end let the kernel prefetch without bounds tests.
+int64_t gram_mixed_table_elems(int64_t N, int p, int n) { return (ceil_div(N, kGmKC) + 3) * p * n * kGmKC; }
 
-// Generate NS samples (from sample s_off of the stage) of one column from
-// the stage's FP32 tables and store its three BF16 terms.
-template <int P, int NS>
-__device__ __forceinline__ void gm_generate(const float* __restrict__ Tb, const int* off, bool valid,
-                                            __bf16* __restrict__ stage, int slot, int s_off) {
-  float v[NS];
-  {
-    const float4* r0 = reinterpret_cast<const float4*>(Tb + off[0] * kG2TabPitch + s_off);
-#pragma unroll
-    for (int q = 0; q < NS / 4; ++q) {
-      const float4 u = r0[q];
-      v[4 * q] = u.x;
-      v[4 * q + 1] = u.y;
-      v[4 * q + 2] = u.z;
-      v[4 * q + 3] = u.w;
-    }
-  }
-#pragma unroll
-  for (int j = 1; j < P; ++j) {
-    const float4* rj = reinterpret_cast<const float4*>(Tb + off[j] * kG2TabPitch + s_off);
-#pragma unroll
-    for (int q = 0; q < NS / 4; ++q) {
-      const float4 u = rj[q];
-      v[4 * q] *= u.x;
-      v[4 * q + 1] *= u.y;
-      v[4 * q + 2] *= u.z;
-      v[4 * q + 3] *= u.w;
-    }
-  }
-  if (!valid) {
-#pragma unroll
-    for (int i = 0; i < NS; ++i) v[i] = 0.0f;
-  }
+// Prefix rows per stage: I-block prefixes then J-half prefixes.
+__host__ __device__ inline int gm_pre_rows_i(int n) { return kGmT / n + 2; }
+__host__ __device__ inline int gm_pre_rows(int n) { return kGmT / n + 2 + kG2H / n + 2; }
+
+static size_t gram_lds_bytes(int p, int n) {
+  return 2 * (size_t)kGmStageElems * sizeof(__bf16) + 3 * (size_t)p * n * kG2TabPitch * sizeof(float) +
+         2 * (size_t)gm_pre_rows(n) * kG2TabPitch * sizeof(float);
+}
+
+// Split NS values into three BF16 terms and store them at [term][slot][s_off..].
+template <int NS>
+__device__ __forceinline__ void gm_store3(const float* v, __bf16* __restrict__ stage, int slot, int s_off) {
   uint32_t h[NS / 2], m[NS / 2], l[NS / 2];
 #pragma unroll
   for (int q = 0; q < NS / 2; ++q) split3(v[2 * q], v[2 * q + 1], h[q], m[q], l[q]);
-  uint4* dh = reinterpret_cast<uint4*>(stage + (0 * kG2Slots + slot) * kG2SlotPitch + s_off);
-  uint4* dm = reinterpret_cast<uint4*>(stage + (1 * kG2Slots + slot) * kG2SlotPitch + s_off);
-  uint4* dl = reinterpret_cast<uint4*>(stage + (2 * kG2Slots + slot) * kG2SlotPitch + s_off);
-#pragma unroll
-  for (int q = 0; q < NS / 8; ++q) {
-    dh[q] = uint4{h[4 * q], h[4 * q + 1], h[4 * q + 2], h[4 * q + 3]};
-    dm[q] = uint4{m[4 * q], m[4 * q + 1], m[4 * q + 2], m[4 * q + 3]};
-    dl[q] = uint4{l[4 * q], l[4 * q + 1], l[4 * q + 2], l[4 * q + 3]};
+  __bf16* dh = stage + (0 * kG2Slots + slot) * kG2SlotPitch + s_off;
+  __bf16* dm = stage + (1 * kG2Slots + slot) * kG2SlotPitch + s_off;
+  __bf16* dl = stage + (2 * kG2Slots + slot) * kG2SlotPitch + s_off;
+  if constexpr (NS == 8) {
+    *reinterpret_cast<uint4*>(dh) = uint4{h[0], h[1], h[2], h[3]};
+    *reinterpret_cast<uint4*>(dm) = uint4{m[0], m[1], m[2], m[3]};
+    *reinterpret_cast<uint4*>(dl) = uint4{l[0], l[1], l[2], l[3]};
+  } else {
+    *reinterpret_cast<uint2*>(dh) = uint2{h[0], h[1]};
+    *reinterpret_cast<uint2*>(dm) = uint2{m[0], m[1]};
+    *reinterpret_cast<uint2*>(dl) = uint2{l[0], l[1]};
   }
 }
 
 template <int P>
-__global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __restrict__ tab32, int64_t N, int n,
-                                                                int M, int T, int split0, float* __restrict__ part) {
+__global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __restrict__ tab32, int64_t N,
+                                                                   int n, int M, int T, int split0,
+                                                                   float* __restrict__ part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smraw[];
-  // LDS: two stage buffers of split Phi, then two stage buffers of 1-D
-  // tables.  Addressed as base + offset so the compiler keeps them in LDS.
+  // LDS: two stage buffers of split Phi, three 1-D table buffers, two prefix
+  // buffers.  Addressed as base + offset so the compiler keeps them in LDS.
   __bf16* const stg0 = reinterpret_cast<__bf16*>(smraw);
   float* const tb0 = reinterpret_cast<float*>(smraw + 2 * kGmStageElems * sizeof(__bf16));
   const int rows = P * n;                       // 1-D table rows per stage
   const int tbs = rows * kG2TabPitch;           // floats per table buffer
+  float* const pr0 = tb0 + 3 * tbs;
+  const int prs = gm_pre_rows(n) * kG2TabPitch; // floats per prefix buffer
   const int tchunks = rows * (kGmKC / 4);       // float4 per stage of the table
 
   int tile = blockIdx.x >> 1, I = 0;
@@ -193,31 +180,28 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __r
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wr = wv >> 1, wc = wv & 1;
 
-  const int colI = I * kGmT + tid;
+  // column ranges and their first prefixes
+  const int cI0 = I * kGmT, cJ0 = J * kGmT + h * kG2H;
+  const int hiI0 = cI0 / n, hiJ0 = cJ0 / n;
+  const int nhiI = (min(cI0 + kGmT, M) - 1) / n - hiI0 + 1;   // prefixes used by the I-block
+  const int nhiJ = diag ? 0 : (min(cJ0 + kG2H, M) - 1) / n - hiJ0 + 1;
+
+  // generation roles: I-block column tid/2, samples (tid&1)*8..+8;
+  // J-half column tid/4, samples (tid&3)*4..+4 (off-diagonal tiles only)
+  const int colI = cI0 + (tid >> 1);
   const bool validI = colI < M;
-  const int colJ = J * kGmT + h * kG2H + (tid >> 1);
+  const int preI = (validI ? colI / n - hiI0 : 0) * kG2TabPitch + (tid & 1) * 8;
+  const int lastI = ((P - 1) * n + (validI ? colI % n : 0)) * kG2TabPitch + (tid & 1) * 8;
+  const int colJ = cJ0 + (tid >> 2);
   const bool genJ = !diag;
   const bool validJ = genJ && colJ < M;
-  int offI[P], offJ[P];
-  {
-    int rem = validI ? colI : 0;
-#pragma unroll
-    for (int j = P - 1; j >= 0; --j) {
-      offI[j] = j * n + rem % n;
-      rem /= n;
-    }
-    rem = validJ ? colJ : 0;
-#pragma unroll
-    for (int j = P - 1; j >= 0; --j) {
-      offJ[j] = j * n + rem % n;
-      rem /= n;
-    }
-  }
+  const int preJ = (gm_pre_rows_i(n) + (validJ ? colJ / n - hiJ0 : 0)) * kG2TabPitch + (tid & 3) * 4;
+  const int lastJ = ((P - 1) * n + (validJ ? colJ % n : 0)) * kG2TabPitch + (tid & 3) * 4;
   const int jslot = diag ? h * kG2H : kGmT;  // B operand columns start here in a stage
 
-  f32x16 acc[4][2], sum[4][2];
+  f32x16 acc[2][2], sum[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -231,47 +215,94 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __r
   if (r1 > N) r1 = N;
   const int nst = (int)ceil_div(r1 - r0, kGmKC);
   const int64_t st0 = r0 / kGmKC;
-  // table stage loader: thread t moves float4 number t and t + 256 (P*n <= 128
-  // rows of 16 floats = at most 512 float4).  The table carries two zero
-  // stages past the last sample, so stage st0 + st + 2 is always readable.
-  auto load_tab = [&](int64_t gst, float4* reg) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int q = tid + u * kG2Threads;
-      if (q < tchunks) reg[u] = reinterpret_cast<const float4*>(tab32 + gst * rows * kGmKC)[q];
+
+  // 1-D tables of one stage: at most 128 rows x 16 floats = 512 float4, one per thread
+  float4 treg;
+  auto load_tab = [&](int64_t gst) {
+    if (tid < tchunks) treg = reinterpret_cast<const float4*>(tab32 + gst * rows * kGmKC)[tid];
+  };
+  auto store_tab = [&](float* dst) {
+    if (tid < tchunks) {
+      const int row = tid / (kGmKC / 4), c4 = tid % (kGmKC / 4);
+      *reinterpret_cast<float4*>(dst + row * kG2TabPitch + c4 * 4) = treg;
     }
   };
-  auto store_tab = [&](float* dst, const float4* reg) {
+  // prefix rows of one stage from its 1-D tables: one (row, 4 samples) per thread
+  auto make_pre = [&](const float* Tb, float* dst) {
+    const int npre = gm_pre_rows(n);
+    for (int u = tid; u < npre * 4; u += kG2Threads) {
+      const int pr = u >> 2, q4 = (u & 3) * 4;
+      int hi = -1;
+      if (pr < nhiI) hi = hiI0 + pr;
+      else if (pr >= gm_pre_rows_i(n) && pr - gm_pre_rows_i(n) < nhiJ) hi = hiJ0 + pr - gm_pre_rows_i(n);
+      float4 v = float4{1.f, 1.f, 1.f, 1.f};
+      if (hi >= 0) {
+        int rem = hi;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int q = tid + u * kG2Threads;
-      if (q < tchunks) {
-        const int row = q / (kGmKC / 4), c4 = q % (kGmKC / 4);
-        *reinterpret_cast<float4*>(dst + row * kG2TabPitch + c4 * 4) = reg[u];
+        for (int j = P - 2; j >= 0; --j) {
+          const float4 f = *reinterpret_cast<const float4*>(Tb + (j * n + rem % n) * kG2TabPitch + q4);
+          v.x *= f.x;
+          v.y *= f.y;
+          v.z *= f.z;
+          v.w *= f.w;
+          rem /= n;
+        }
       }
+      *reinterpret_cast<float4*>(dst + pr * kG2TabPitch + q4) = v;
     }
   };
-  // Rows of stages past the chunk end must not enter the sum: stages st >= nst
-  // are never multiplied, and the chunk's own last stage is zero-padded by the
-  // table (samples >= N) or ends exactly at a chunk boundary (chunks are
-  // multiples of 16).
-  float4 treg[2];
-  load_tab(st0, treg);
-  store_tab(tb0, treg);
-  load_tab(st0 + 1, treg);
-  store_tab(tb0 + tbs, treg);
+  auto generate = [&](const float* Tb, const float* Pr, __bf16* D) {
+    {
+      float v[8];
+      const float4* pa = reinterpret_cast<const float4*>(Pr + preI);
+      const float4* la = reinterpret_cast<const float4*>(Tb + lastI);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const float4 a = pa[q], b = la[q];
+        v[4 * q] = a.x * b.x;
+        v[4 * q + 1] = a.y * b.y;
+        v[4 * q + 2] = a.z * b.z;
+        v[4 * q + 3] = a.w * b.w;
+      }
+      if (!validI) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = 0.0f;
+      }
+      gm_store3<8>(v, D, tid >> 1, (tid & 1) * 8);
+    }
+    if (genJ) {
+      float v[4];
+      const float4 a = *reinterpret_cast<const float4*>(Pr + preJ);
+      const float4 b = *reinterpret_cast<const float4*>(Tb + lastJ);
+      v[0] = a.x * b.x;
+      v[1] = a.y * b.y;
+      v[2] = a.z * b.z;
+      v[3] = a.w * b.w;
+      if (!validJ) v[0] = v[1] = v[2] = v[3] = 0.0f;
+      gm_store3<4>(v, D, kGmT + (tid >> 2), (tid & 3) * 4);
+    }
+  };
+
+  // prologue: tables of stages 0..2, prefixes of stages 0..1, Phi of stage 0
+  load_tab(st0);
+  store_tab(tb0);
+  load_tab(st0 + 1);
+  store_tab(tb0 + tbs);
+  load_tab(st0 + 2);
+  store_tab(tb0 + 2 * tbs);
   __syncthreads();
-  gm_generate<P, 16>(tb0, offI, validI, stg0, tid, 0);
-  if (genJ) gm_generate<P, 8>(tb0, offJ, validJ, stg0, kGmT + (tid >> 1), (tid & 1) * 8);
+  make_pre(tb0, pr0);
+  make_pre(tb0 + tbs, pr0 + prs);
+  __syncthreads();
+  generate(tb0, pr0, stg0);
   __syncthreads();
 
   for (int g0 = 0; g0 < nst; g0 += kG2Flush) {
     const int gend = min(g0 + kG2Flush, nst);
     for (int st = g0; st < gend; ++st) {
-      // stream the tables of stage st+2 while this stage computes
-      load_tab(st0 + st + 2, treg);
+      load_tab(st0 + st + 3);
       const __bf16* S = stg0 + (st & 1) * kGmStageElems;
-      bf16x8 bop[2][3];
+      bf16x8 aop[2][3], bop[2][3];
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -279,36 +310,44 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __r
           bop[cb][q] = *reinterpret_cast<const bf16x8*>(
               S + (q * kG2Slots + jslot + wc * 64 + cb * 32 + (lane & 31)) * kG2SlotPitch + (lane >> 5) * 8);
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        bf16x8 aop[3];
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int q = 0; q < 3; ++q)
-          aop[q] = *reinterpret_cast<const bf16x8*>(
-              S + (q * kG2Slots + wr * 128 + rb * 32 + (lane & 31)) * kG2SlotPitch + (lane >> 5) * 8);
+          aop[rb][q] = *reinterpret_cast<const bf16x8*>(
+              S + (q * kG2Slots + wr * 64 + rb * 32 + (lane & 31)) * kG2SlotPitch + (lane >> 5) * 8);
+      // six products, interleaved over the four accumulators
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          f32x16 c = acc[rb][cb];
-          c = mfma_bf16(aop[1], bop[cb][1], c);  // mid*mid
-          c = mfma_bf16(aop[2], bop[cb][0], c);  // lo*hi
-          c = mfma_bf16(aop[0], bop[cb][2], c);  // hi*lo
-          c = mfma_bf16(aop[1], bop[cb][0], c);  // mid*hi
-          c = mfma_bf16(aop[0], bop[cb][1], c);  // hi*mid
-          c = mfma_bf16(aop[0], bop[cb][0], c);  // hi*hi
-          acc[rb][cb] = c;
-        }
-      }
-      // generate stage st+1 (past the chunk end this produces unused zeros)
-      {
-        __bf16* D = stg0 + ((st + 1) & 1) * kGmStageElems;
-        const float* Tn = tb0 + ((st + 1) & 1) * tbs;
-        gm_generate<P, 16>(Tn, offI, validI, D, tid, 0);
-        if (genJ) gm_generate<P, 8>(Tn, offJ, validJ, D, kGmT + (tid >> 1), (tid & 1) * 8);
-      }
-      store_tab(tb0 + (st & 1) * tbs, treg);
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][1], bop[cb][1], acc[rb][cb]);  // mid*mid
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][2], bop[cb][0], acc[rb][cb]);  // lo*hi
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][2], acc[rb][cb]);  // hi*lo
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][1], bop[cb][0], acc[rb][cb]);  // mid*hi
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][1], acc[rb][cb]);  // hi*mid
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][0], acc[rb][cb]);  // hi*hi
+      // stage st+1 (past the chunk end this produces unused values)
+      generate(tb0 + ((st + 1) % 3) * tbs, pr0 + ((st + 1) & 1) * prs, stg0 + ((st + 1) & 1) * kGmStageElems);
+      make_pre(tb0 + ((st + 2) % 3) * tbs, pr0 + (st & 1) * prs);
+      store_tab(tb0 + (st % 3) * tbs);
       __syncthreads();
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -321,12 +360,12 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __r
   const int ntiles = T * (T + 1) / 2;
   float* out = part + ((int64_t)blockIdx.y * ntiles + (blockIdx.x >> 1)) * (kGmT * kGmT);
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = wr * 128 + rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int row = wr * 64 + rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int cl = h * kG2H + wc * 64 + cb * 32 + (lane & 31);
         out[row * kGmT + cl] = sum[rb][cb][r];
       }
@@ -366,8 +405,8 @@ __global__ void gram_mixed_reduce_kernel(const float* __restrict__ part, int spl
 void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const double* tab, const double* reg,
                        float* part, float* tab32, double* A, hipStream_t s, Prof* prof) {
   const GramPlan g = gram_mixed_plan(N, M);
-  const int64_t nstage = ceil_div(N, kGmKC) + 2;
-  const size_t lds = 2 * kGmStageElems * sizeof(__bf16) + 2 * (size_t)p * n * kG2TabPitch * sizeof(float);
+  const int64_t nstage = ceil_div(N, kGmKC) + 3;
+  const size_t lds = gram_lds_bytes(p, n);
   prof_mark(prof, GP_PH_GRAM, true, s);
   hipLaunchKernelGGL(phi1d_table_kernel, dim3(ceil_div(nstage * p * kGmKC, 256)), dim3(256), 0, s, x, N, p, n, tab,
                      tab32, nstage);

@@ -102,6 +102,25 @@ def test_c1_stages_fp64(torch_cuda, ctx):
     assert np.abs(Li @ L - np.eye(P.M)).max() <= 1e-10
 
 
+@pytest.mark.parametrize("seed,p,n,N", [(21, 2, 17, 3000), (22, 3, 11, 6000), (23, 1, 64, 500), (24, 2, 45, 8000)])
+def test_factor_stages_multiblock(torch_cuda, ctx, seed, p, n, N):
+    """Cholesky and L^-1 across several 64-blocks and recursion levels,
+    including ragged last blocks (M = 289, 1331, 64, 2025)."""
+    P = wl.random_problem(seed, p, n, N, 10)
+    m, _, _ = gpu_fit_predict(torch_cuda, ctx, P, B.PREC_FP64)
+    A = m.get(B.MODEL_A)
+    L = m.get(B.MODEL_L)
+    Li = m.get(B.MODEL_LINV)
+    f = o.fit(P.x, P.y, P.sigma, P.eps, P.alpha, P.n)
+    assert rel(A, f.A) <= 1e-12
+    assert np.allclose(np.triu(L, 1), 0.0) and np.allclose(np.triu(Li, 1), 0.0)
+    assert rel(L @ L.T, A) <= 1e-13
+    # L^-1 L = I to rounding, measured against |L^-1| |L| (scale-free)
+    E = np.abs(Li @ L - np.eye(P.M)) / (np.abs(Li) @ np.abs(L) + 1e-300)
+    print(f"[err] stages {P.name}: max |Li L - I| / (|Li||L|) = {E.max():.3e}", flush=True)
+    assert E.max() <= 1e-12
+
+
 @pytest.mark.parametrize("seed,p,n,N,Ns", [
     (1, 1, 1, 1, 1),          # smallest problem
     (2, 1, 7, 5, 3),          # M > N
