@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-target-s", type=float, default=15.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the served Poisson stream (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -67,6 +70,102 @@ def run_path(ctx, torch, P, dev, precision, steps, warmup):
     prof = ctx.profile_read()
     ctx.profile(False)
     return dt, prof, (mean, var)
+
+
+def served_stream(torch, rate, seconds, warm=2.0):
+    """Poisson arrivals of fit+predict requests through gp_submit / gp_poll:
+    p ~ U{2..5}, n = 6, N log-U[1e3, 5e5], N* log-U[1e2, 1e5], x ~ U[-1,1]^p,
+    y = exp(-|x|^2) + cos(3 x1 x2) + N(0, 0.05^2), sigma = 0.05, eps = 1,
+    alpha = 1.2, mixed precision.  Inputs are slices of seeded device-resident
+    pools (drawn before the stream starts).  Returns latency percentiles and
+    sustained points/s over the requests that arrived after the warm-up."""
+    import threading
+    from paper_2403_12797_amd import binding as B
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence(12797 + 5)))
+    NMAX, NSMAX = 500_000, 100_000
+    pools = {}
+    for p in range(2, 6):
+        x = g.uniform(-1.0, 1.0, size=(NMAX, p))
+        y = np.exp(-(x * x).sum(axis=1)) + np.cos(3.0 * x[:, 0] * x[:, 1]) + g.normal(0.0, 0.05, size=NMAX)
+        xs = g.uniform(-1.0, 1.0, size=(NSMAX, p))
+        pools[p] = tuple(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (x, y, xs))
+    out_mean = torch.empty(NSMAX, dtype=torch.float64, device="cuda")
+    total = warm + seconds
+    reqs = []
+    t = 0.0
+    while True:
+        t += g.exponential(1.0 / rate)
+        if t >= total:
+            break
+        p = int(g.integers(2, 6))
+        N = int(round(10 ** g.uniform(3.0, np.log10(NMAX))))
+        Ns = int(round(10 ** g.uniform(2.0, np.log10(NSMAX))))
+        off = int(g.integers(0, NMAX - N + 1))
+        offs = int(g.integers(0, NSMAX - Ns + 1))
+        reqs.append((t, p, N, Ns, off, offs))
+    torch.cuda.synchronize()
+    ctx = B.Context(0)
+    prm = {p: B.make_params(p, 6, 0.05, 1.0, 1.2, B.PREC_MIXED) for p in range(2, 6)}
+    means = [torch.empty(r[3], dtype=torch.float64, device="cuda") for r in reqs]
+    vars_ = [torch.empty(r[3], dtype=torch.float64, device="cuda") for r in reqs]
+    ids = [None] * len(reqs)
+    t_sub = [0.0] * len(reqs)
+    t_done = [0.0] * len(reqs)
+    status = [None] * len(reqs)
+    submitted = threading.Semaphore(0)
+
+    def submitter():
+        t0 = time.perf_counter()
+        for k, (ta, p, N, Ns, off, offs) in enumerate(reqs):
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            x, y, xs = pools[p]
+            t_sub[k] = time.perf_counter()
+            ids[k] = ctx.submit(B.REQ_FIT_PREDICT, x=x[off:off + N], y=y[off:off + N], params=prm[p],
+                                xs=xs[offs:offs + Ns], mean=means[k], var=vars_[k])
+            submitted.release()
+
+    th = threading.Thread(target=submitter)
+    t_start = time.perf_counter()
+    th.start()
+    # poll every outstanding request without blocking, so each completion is
+    # stamped when it happens (requests can finish out of order)
+    outstanding = []
+    nxt = 0
+    done_count = 0
+    while done_count < len(reqs):
+        while submitted.acquire(blocking=False):
+            outstanding.append(nxt)
+            nxt += 1
+        progressed = False
+        for k in list(outstanding):
+            try:
+                st, _ = ctx.poll(ids[k], wait_us=0)
+            except B.GpError as e:
+                st = e.status
+            if st != B.GP_PENDING:
+                t_done[k] = time.perf_counter()
+                status[k] = st
+                outstanding.remove(k)
+                done_count += 1
+                progressed = True
+        if not progressed:
+            time.sleep(0.0002)
+    th.join()
+    t_end = time.perf_counter()
+    ctx.close()
+    sel = [k for k in range(len(reqs)) if reqs[k][0] >= warm]
+    lat = np.array([t_done[k] - t_sub[k] for k in sel]) * 1e3
+    pts = sum(reqs[k][2] + reqs[k][3] for k in sel)
+    span = max(t_done[k] for k in sel) - min(t_sub[k] for k in sel)
+    return {"requests": len(sel), "rate_req_s": rate, "seconds": seconds,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "points_per_s": pts / span,
+            "failed": int(sum(1 for k in sel if status[k] != B.GP_OK)),
+            "wall_s": t_end - t_start,
+            "workload": "Poisson 200 req/s fit+predict, p~U{2..5}, n=6 (M<=7776), N log-U[1e3,5e5], "
+                        "N* log-U[1e2,1e5], mixed precision, 4 stream slots"}
 
 
 def cpu_baseline(P_full, target_s):
@@ -164,8 +263,13 @@ def main():
                      "predict_kernel_frac": (P.Ns * P.M * (P.M + 1)) / (pv_ms * 1e-3) / PEAK_BF16},
         "phases_ms": {k: round(v[0] / steps, 3) for k, v in prof_mx.items() if v[1]},
         "fp64_path": fp64,
+        "served": None,
         "cpu_baseline": None if a.no_cpu else cpu_baseline(P, a.cpu_target_s),
     }
+    if a.serve_seconds > 0:
+        print(f"[bench] served stream {a.serve_seconds:.0f} s at {a.serve_rate:.0f} req/s", file=sys.stderr,
+              flush=True)
+        out["served"] = served_stream(torch, a.serve_rate, a.serve_seconds)
     print(json.dumps(out), flush=True)
 
 

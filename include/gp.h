@@ -134,6 +134,31 @@ enum { GP_MODEL_W = 0, GP_MODEL_LAMBDA = 1, GP_MODEL_A = 2, GP_MODEL_B = 3, GP_M
        GP_MODEL_LINV = 5 };
 gp_status gp_model_get(const gp_model *model, int32_t what, double *host_out, int64_t count);
 
+/* Batched fit of `count` independent problems (uneven N, p, n allowed):
+ * params/x/y/N/out_models are arrays of length count (x[k], y[k] device
+ * arrays as in gp_fit).  The mixed-precision problems share one persistent
+ * Gram launch over all their tiles (work list, longest first); the whole
+ * batch runs as one captured HIP graph.  Waits for completion.  Each
+ * out_models[k] is a new model; on an error the failing problem's model is
+ * NULL and the first error is returned (other models stay valid).
+ * Errors: as gp_fit, with the problem index in the message.               */
+gp_status gp_fit_batch(gp_ctx *ctx, int32_t count, const gp_params *params, const double *const *x,
+                       const double *const *y, const int64_t *N, void *stream, gp_model **out_models);
+
+/* Batched predict: as gp_predict for each k (mean/var may be NULL arrays or
+ * hold NULL entries); enqueued on `stream`, returns without waiting.        */
+gp_status gp_predict_batch(gp_ctx *ctx, int32_t count, const gp_model *const *models,
+                           const double *const *xs, const int64_t *Ns, double *const *mean,
+                           double *const *var, void *stream);
+
+/* Autotuner: time the split-BF16 Gram kernel for (p, n, N) on synthetic
+ * inputs at several sample-chunk lengths and keep the fastest for later fits
+ * of this context with the same p, n and floor(log2 N) (and in the file named
+ * by the environment variable MGP_TUNE_CACHE, read at context creation).
+ * *chunk_out (may be NULL) receives the chosen chunk.  Errors: GP_EINVAL,
+ * GP_ENOMEM, GP_EDEVICE.                                                     */
+gp_status gp_autotune(gp_ctx *ctx, int32_t p, int32_t n, int64_t N, int32_t *chunk_out);
+
 /* Served path: asynchronous requests with continuous batching.
  *  kind   GP_REQ_FIT (x, y, N -> model), GP_REQ_PREDICT (model, xs, Ns ->
  *         mean/var), GP_REQ_FIT_PREDICT (both; the model is kept only if

@@ -23,7 +23,8 @@ REQ_FIT, REQ_PREDICT, REQ_FIT_PREDICT = 0, 1, 2
 MAX_P, MAX_N, MAX_M = 8, 64, 16384
 
 EXPORTED = ["gp_ctx_create", "gp_ctx_destroy", "gp_fit", "gp_predict", "gp_model_free", "gp_model_info",
-            "gp_model_get", "gp_submit", "gp_poll", "gp_last_error", "gp_profile_enable", "gp_profile_read"]
+            "gp_model_get", "gp_submit", "gp_poll", "gp_last_error", "gp_profile_enable", "gp_profile_read",
+            "gp_fit_batch", "gp_predict_batch", "gp_autotune"]
 PHASES = ["gram", "gram_reduce", "phiT", "chol", "trtri", "solve", "split", "predict", "predict_mean",
           "predict_reduce"]
 
@@ -71,6 +72,11 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "gp_last_error": (C.c_char_p, []),
         "gp_profile_enable": (i32, [vp, i32]),
         "gp_profile_read": (i32, [vp, i32, dp, C.POINTER(i64)]),
+        "gp_fit_batch": (i32, [vp, i32, C.POINTER(GpParams), C.POINTER(vp), C.POINTER(vp), C.POINTER(i64), vp,
+                               C.POINTER(vp)]),
+        "gp_predict_batch": (i32, [vp, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64), C.POINTER(vp),
+                                   C.POINTER(vp), vp]),
+        "gp_autotune": (i32, [vp, i32, i32, i64, C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -185,6 +191,41 @@ class Context:
         _check(load().gp_predict(self.handle, model.handle, _ptr(xs), Ns, _ptr(mean), _ptr(var),
                                  _stream(stream)))
         return mean, var
+
+    def autotune(self, p: int, n: int, N: int) -> int:
+        c = C.c_int32()
+        _check(load().gp_autotune(self.handle, p, n, N, C.byref(c)))
+        return c.value
+
+    def fit_batch(self, problems, precision=PREC_MIXED, stream=None):
+        """problems: list of (x, y, p, n, sigma, eps, alpha) with device x, y."""
+        k = len(problems)
+        prms = (GpParams * k)()
+        keep = []
+        for i, (x, y, p, n, sigma, eps, alpha) in enumerate(problems):
+            prm = make_params(p, n, sigma, eps, alpha, precision)
+            keep.append(prm._keep)
+            prms[i] = prm
+        xs = (C.c_void_p * k)(*[_ptr(pr[0]).value for pr in problems])
+        ys = (C.c_void_p * k)(*[_ptr(pr[1]).value for pr in problems])
+        Ns = (C.c_int64 * k)(*[pr[1].shape[0] for pr in problems])
+        out = (C.c_void_p * k)()
+        st = load().gp_fit_batch(self.handle, k, prms, xs, ys, Ns, _stream(stream), out)
+        models = [Model(C.c_void_p(out[i])) if out[i] else None for i in range(k)]
+        if st < 0:
+            err = GpError(st, last_error())
+            err.models = models
+            raise err
+        return models
+
+    def predict_batch(self, models, xs_list, means, vars_, stream=None):
+        k = len(models)
+        hs = (C.c_void_p * k)(*[m.handle.value if isinstance(m.handle, C.c_void_p) else m.handle for m in models])
+        xs = (C.c_void_p * k)(*[_ptr(x).value for x in xs_list])
+        Ns = (C.c_int64 * k)(*[x.shape[0] for x in xs_list])
+        mp = (C.c_void_p * k)(*[(_ptr(m).value if m is not None else None) for m in means])
+        vp_ = (C.c_void_p * k)(*[(_ptr(v).value if v is not None else None) for v in vars_])
+        _check(load().gp_predict_batch(self.handle, k, hs, xs, Ns, mp, vp_, _stream(stream)))
 
     def submit(self, kind, *, x=None, y=None, params=None, model=None, xs=None, mean=None, var=None) -> int:
         req = GpRequest()

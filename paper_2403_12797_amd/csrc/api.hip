@@ -62,14 +62,38 @@ size_t model_bytes(int64_t M, int precision) {
   return b;
 }
 
-// Transient device bytes of a fit / predict.
-size_t fit_workspace_bytes(int64_t N, int p, int n, int64_t M, int precision) {
-  size_t g = precision == GP_PREC_MIXED ? (size_t)gram_mixed_part_elems(N, (int)M, nullptr) * 4 +
-                                              (size_t)gram_mixed_table_elems(N, p, n) * 4 + 256
-                                        : (size_t)gram_f64_part_elems(N, (int)M, nullptr) * 8;
-  size_t v = (size_t)phiT_part_elems(N, (int)M) * 8 + (size_t)N * 8 + 4 * (size_t)M * 8 +
-             (size_t)ceil_div(M, 256) * M * 8 + trtri_workspace_elems((int)M) * 8;
-  return g + v + 2048;
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chunk, bool all_splits) {
+  FitLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o += align_up(bytes);
+    return r;
+  };
+  if (precision == GP_PREC_MIXED) {
+    L.g = gram_mixed_plan(N, (int)M, chunk);
+    if (all_splits) L.g.splits_per_pass = L.g.splits_total, L.g.passes = 1;
+    L.gpart = take((size_t)gram_mixed_part_elems(L.g) * 4);
+    L.tab32 = take((size_t)gram_mixed_table_elems(N, p, n) * 4);
+  } else {
+    L.gpart = take((size_t)gram_f64_part_elems(N, (int)M, nullptr) * 8);
+    L.tab32 = take(0);
+  }
+  L.vpart = take((size_t)phiT_part_elems(N, (int)M) * 8);
+  L.resid = take((size_t)N * 8);
+  L.z = take((size_t)M * 8);
+  L.r = take((size_t)M * 8);
+  L.d = take((size_t)M * 8);
+  L.ltpart = take((size_t)ceil_div(M, 256) * M * 8);
+  L.trws = take(trtri_workspace_elems((int)M) * 8);
+  L.total = o + 256;
+  return L;
+}
+
+size_t fit_workspace_bytes(gp_ctx* ctx, int64_t N, int p, int n, int64_t M, int precision) {
+  return fit_layout(N, p, n, M, precision, tuned_chunk(ctx, p, n, N), false).total;
 }
 
 size_t predict_workspace_bytes(int64_t Ns, int64_t M, int precision) {
@@ -79,8 +103,6 @@ size_t predict_workspace_bytes(int64_t Ns, int64_t M, int precision) {
              8 +
          256;
 }
-
-static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 void prof_mark(Prof* p, int phase, bool begin, hipStream_t s) {
   if (!p || !p->on) return;
@@ -158,9 +180,10 @@ gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t 
   return GP_OK;
 }
 
-// Enqueue the whole fit on stream s.  ws must hold fit_workspace_bytes().
-// flags[0] = Cholesky info, flags[1] = non-finite input.
-void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void* ws, hipStream_t s) {
+// The fit in three parts so that many problems can share the Gram launch.
+// head: flags, input checks, eigen tables (and the FP32 1-D tables, mixed).
+void enqueue_fit_head(gp_model* m, const double* x, const double* y, int64_t N, const FitLayout& L, void* ws,
+                      hipStream_t s) {
   const int p = m->p, n = m->n, M = (int)m->M;
   EigArgs a;
   memset(&a, 0, sizeof(a));
@@ -172,38 +195,29 @@ void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void*
     a.alpha[j] = m->alpha[j];
   }
   char* wb = (char*)ws;
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    void* r = wb + o;
-    o += align_up(bytes);
-    return r;
-  };
-  const size_t gbytes = m->precision == GP_PREC_MIXED ? (size_t)gram_mixed_part_elems(N, M, nullptr) * 4
-                                                      : (size_t)gram_f64_part_elems(N, M, nullptr) * 8;
-  void* gpart = take(gbytes);
-  float* tab32 = m->precision == GP_PREC_MIXED ? (float*)take((size_t)gram_mixed_table_elems(N, p, n) * 4) : nullptr;
-  double* vpart = (double*)take((size_t)phiT_part_elems(N, M) * 8);
-  double* resid = (double*)take((size_t)N * 8);
-  double* z = (double*)take((size_t)M * 8);
-  double* r = (double*)take((size_t)M * 8);
-  double* d = (double*)take((size_t)M * 8);
-  double* ltpart = (double*)take((size_t)ceil_div(M, 256) * M * 8);
-  double* trws = (double*)take(trtri_workspace_elems(M) * 8);
-
-  Prof* pr = &m->ctx->prof;
-  hipMemsetAsync(m->flags, 0, 64, s);
+  launch_fill_zero_int(m->flags, 16, s);
   launch_check_finite(x, N * p, m->flags + 1, s);
   launch_check_finite(y, N, m->flags + 1, s);
   launch_eig_tables(a, m->tab, m->lam, m->reg, M, s);
-  // a3: A = Phi^T Phi + sigma^2 Lambda^-1, b = Phi^T y
-  if (m->precision == GP_PREC_MIXED)
-    launch_gram_mixed(x, N, p, n, M, m->tab, m->reg, (float*)gpart, tab32, m->A, s, pr);
-  else
-    launch_gram_f64(x, N, p, n, M, m->tab, m->reg, (double*)gpart, m->A, s, pr);
+  if (m->precision == GP_PREC_MIXED) launch_gram_mixed_table(x, N, p, n, m->tab, (float*)(wb + L.tab32), s);
+}
+
+// tail: b = Phi^T y, Cholesky, L^-1, w with one FP64 refinement step, BF16 split.
+void enqueue_fit_tail(gp_model* m, const double* x, const double* y, int64_t N, const FitLayout& L, void* ws,
+                      hipStream_t s) {
+  const int p = m->p, n = m->n, M = (int)m->M;
+  char* wb = (char*)ws;
+  double* vpart = (double*)(wb + L.vpart);
+  double* resid = (double*)(wb + L.resid);
+  double* z = (double*)(wb + L.z);
+  double* r = (double*)(wb + L.r);
+  double* d = (double*)(wb + L.d);
+  double* ltpart = (double*)(wb + L.ltpart);
+  double* trws = (double*)(wb + L.trws);
+  Prof* pr = &m->ctx->prof;
   prof_mark(pr, GP_PH_PHIT, true, s);
   launch_phiT_vec(x, y, N, p, n, M, m->tab, vpart, nullptr, nullptr, m->b, s);
   prof_mark(pr, GP_PH_PHIT, false, s);
-  // a4: L L^T = A, L^-1, w = L^-T L^-1 b, one refinement with the FP64 residual
   prof_mark(pr, GP_PH_CHOL, true, s);
   hipMemcpyAsync(m->L, m->A, (size_t)M * M * 8, hipMemcpyDeviceToDevice, s);
   launch_cholesky(m->L, M, m->Dinv, m->flags, s);
@@ -225,6 +239,24 @@ void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void*
     launch_split_linv(m->Linv, m->linv_pieces, M, s);
     prof_mark(pr, GP_PH_SPLIT, false, s);
   }
+}
+
+// Enqueue the whole fit of one problem on stream s.  ws must hold
+// fit_workspace_bytes() for the same context.
+void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void* ws, hipStream_t s) {
+  const int p = m->p, n = m->n, M = (int)m->M;
+  const FitLayout L = fit_layout(N, p, n, M, m->precision, tuned_chunk(m->ctx, p, n, N), false);
+  char* wb = (char*)ws;
+  Prof* pr = &m->ctx->prof;
+  enqueue_fit_head(m, x, y, N, L, ws, s);
+  // a3: A = Phi^T Phi + sigma^2 Lambda^-1
+  if (m->precision == GP_PREC_MIXED) {
+    launch_gram_mixed(x, N, p, n, M, L.g, m->tab, m->reg, (float*)(wb + L.gpart), (float*)(wb + L.tab32), m->A, s,
+                      pr);
+  } else {
+    launch_gram_f64(x, N, p, n, M, m->tab, m->reg, (double*)(wb + L.gpart), m->A, s, pr);
+  }
+  enqueue_fit_tail(m, x, y, N, L, ws, s);
 }
 
 void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* mean, double* var, void* ws,
@@ -272,6 +304,7 @@ gp_status gp_ctx_create(int device, size_t hbm_budget_bytes, gp_ctx** out) {
     uint64_t thr = UINT64_MAX;
     hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
   }
+  tune_load(c);
   gp_status st = scheduler_start(c);
   if (st != GP_OK) {
     delete c;
@@ -304,7 +337,7 @@ gp_status gp_fit(gp_ctx* ctx, const gp_params* params, const double* x, const do
   st = model_alloc(ctx, params, M, s, &m);
   if (st != GP_OK) return st;
   void* ws = nullptr;
-  const size_t wsb = fit_workspace_bytes(N, params->p, params->n, M, params->precision);
+  const size_t wsb = fit_workspace_bytes(ctx, N, params->p, params->n, M, params->precision);
   hipError_t e = hipMallocAsync(&ws, wsb, s);
   if (e != hipSuccess) {
     gp_model_free(m);

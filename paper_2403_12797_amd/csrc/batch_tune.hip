@@ -1,0 +1,368 @@
+// Batched fit / predict of many independent problems, and the Gram-chunk
+// autotuner.
+//
+// gp_fit_batch: every problem's eigen tables and 1-D tables, then ONE
+// persistent split-BF16 Gram launch over the work items of all mixed
+// problems (longest first, pulled through an atomic counter), then each
+// problem's reduction, Cholesky, L^-1, solves and refinement on forked
+// streams.  The whole sequence is captured into a HIP graph and launched
+// once.
+#include <algorithm>
+#include <chrono>
+#include <fstream>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <vector>
+
+#include "kernels.h"
+#include "runtime.h"
+
+namespace mgp {
+
+
+// ---------------------------------------------------------------- autotuner
+static int64_t tune_key(int p, int n, int64_t N) {
+  int b = 0;
+  while (b < 62 && (int64_t(1) << (b + 1)) <= N) ++b;
+  return ((int64_t)p << 40) | ((int64_t)n << 32) | b;
+}
+
+int tuned_chunk(gp_ctx* ctx, int p, int n, int64_t N) {
+  if (!ctx) return 0;
+  std::lock_guard<std::mutex> lk(ctx->tune_mu);
+  auto it = ctx->tune.find(tune_key(p, n, N));
+  return it == ctx->tune.end() ? 0 : it->second;
+}
+
+// Cache file: one "p n log2N chunk" line per entry.
+void tune_load(gp_ctx* ctx) {
+  const char* path = getenv("MGP_TUNE_CACHE");
+  if (!path || !*path) return;
+  ctx->tune_path = path;
+  std::ifstream f(path);
+  int p, n, b, c;
+  while (f >> p >> n >> b >> c)
+    if (p > 0 && n > 0 && c > 0) ctx->tune[((int64_t)p << 40) | ((int64_t)n << 32) | b] = c;
+}
+
+static void tune_save(gp_ctx* ctx) {
+  if (ctx->tune_path.empty()) return;
+  std::ofstream f(ctx->tune_path);
+  for (auto& kv : ctx->tune)
+    f << (kv.first >> 40) << " " << ((kv.first >> 32) & 0xff) << " " << (kv.first & 0xffffffff) << " " << kv.second
+      << "\n";
+}
+
+__global__ void synth_x_kernel(double* __restrict__ x, int64_t count, uint32_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)i * 2654435761u ^ seed;
+    h ^= h >> 16;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    h *= 3266489917u;
+    h ^= h >> 16;
+    x[i] = 2.0 * ((double)h * (1.0 / 4294967296.0)) - 1.0;
+  }
+}
+
+}  // namespace mgp
+
+using namespace mgp;
+
+extern "C" {
+
+gp_status gp_autotune(gp_ctx* ctx, int32_t p, int32_t n, int64_t N, int32_t* chunk_out) {
+  if (!ctx) return fail(GP_EINVAL, "ctx is NULL");
+  double one[GP_MAX_P];
+  for (int j = 0; j < GP_MAX_P; ++j) one[j] = 1.0;
+  gp_params prm{p, n, 0.1, one, one, GP_PREC_MIXED};
+  int64_t M = 0;
+  gp_status st = validate_params(&prm, &M);
+  if (st != GP_OK) return st;
+  if (N < 16) return fail(GP_EINVAL, "N=%lld too small to tune", (long long)N);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(GP_EDEVICE, "hipSetDevice");
+  hipStream_t s;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fail(GP_EDEVICE, "stream");
+  const int cands[] = {1024, 2048, 4096, 8192, 16384, 32768};
+  // workspace for the smallest chunk (most partials) plus x and the tables
+  GramPlan g0 = gram_mixed_plan(N, (int)M, cands[0]);
+  size_t part_b = (size_t)gram_mixed_part_elems(g0) * 4;
+  const size_t tab_b = (size_t)gram_mixed_table_elems(N, p, n) * 4;
+  const size_t x_b = (size_t)N * p * 8;
+  const size_t misc = (size_t)(kTabSize + 2 * M + M * M) * 8;
+  char* buf = nullptr;
+  if (hipMallocAsync((void**)&buf, part_b + tab_b + x_b + misc + 4096, s) != hipSuccess) {
+    hipStreamDestroy(s);
+    return fail(GP_ENOMEM, "autotune workspace");
+  }
+  float* part = (float*)buf;
+  float* tab32 = (float*)(buf + ((part_b + 255) & ~(size_t)255));
+  double* x = (double*)((char*)tab32 + ((tab_b + 255) & ~(size_t)255));
+  double* tab = (double*)((char*)x + ((x_b + 255) & ~(size_t)255));
+  double* lam = tab + kTabSize;
+  double* reg = lam + M;
+  double* A = reg + M;
+  hipLaunchKernelGGL(synth_x_kernel, dim3(1024), dim3(256), 0, s, x, N * p, 12797u);
+  EigArgs a;
+  memset(&a, 0, sizeof(a));
+  a.p = p;
+  a.n = n;
+  a.sigma = 0.1;
+  for (int j = 0; j < p; ++j) a.eps[j] = a.alpha[j] = 1.0;
+  launch_eig_tables(a, tab, lam, reg, (int)M, s);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int c : cands) {
+    if (c > 2 * ceil_div(N, 16) * 16 && best) break;
+    GramPlan g = gram_mixed_plan(N, (int)M, c);
+    if ((size_t)gram_mixed_part_elems(g) * 4 > part_b) continue;
+    float tot = 0.0f;
+    for (int rep = 0; rep < 3; ++rep) {
+      hipEventRecord(e0, s);
+      launch_gram_mixed(x, N, p, n, (int)M, g, tab, reg, part, tab32, A, s, nullptr);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) tot += ms;  // first run is a warm-up
+    }
+    if (tot < best_ms) {
+      best_ms = tot;
+      best = g.chunk;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFreeAsync(buf, s);
+  hipStreamSynchronize(s);
+  hipStreamDestroy(s);
+  if (!best) return fail(GP_EDEVICE, "autotune found no candidate");
+  {
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    ctx->tune[tune_key(p, n, N)] = best;
+    tune_save(ctx);
+  }
+  if (chunk_out) *chunk_out = best;
+  return GP_OK;
+}
+
+gp_status gp_fit_batch(gp_ctx* ctx, int32_t count, const gp_params* params, const double* const* x,
+                       const double* const* y, const int64_t* N, void* stream, gp_model** out_models) {
+  if (!ctx || count < 0 || (count > 0 && (!params || !x || !y || !N || !out_models)))
+    return fail(GP_EINVAL, "gp_fit_batch: NULL argument or negative count");
+  for (int k = 0; k < count; ++k) out_models[k] = nullptr;
+  if (count == 0) return GP_OK;
+  std::vector<int64_t> Ms(count);
+  for (int k = 0; k < count; ++k) {
+    gp_status st = validate_params(&params[k], &Ms[k]);
+    if (st != GP_OK) return fail(st, "problem %d: %s", k, gp_last_error());
+    if (N[k] < 1 || !x[k] || !y[k]) return fail(GP_EINVAL, "problem %d: needs x, y and N >= 1", k);
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(GP_EDEVICE, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  // models and one workspace block for all problems
+  std::vector<gp_model*> ms(count, nullptr);
+  std::vector<FitLayout> Ls(count);
+  std::vector<size_t> off(count);
+  size_t total = 0;
+  for (int k = 0; k < count; ++k) {
+    gp_status st = model_alloc(ctx, &params[k], Ms[k], s, &ms[k]);
+    if (st != GP_OK) {
+      for (int q = 0; q < k; ++q) model_release(ms[q], s, true);
+      return st;
+    }
+    Ls[k] = fit_layout(N[k], params[k].p, params[k].n, Ms[k], params[k].precision,
+                       tuned_chunk(ctx, params[k].p, params[k].n, N[k]), true);
+    off[k] = total;
+    total += (Ls[k].total + 255) & ~(size_t)255;
+  }
+  // batched Gram work list (mixed problems)
+  std::vector<GramProb> probs;
+  std::vector<GramItem> items;
+  std::vector<int> prob_of(count, -1);
+  size_t lds = 0;
+  for (int k = 0; k < count; ++k) {
+    if (params[k].precision != GP_PREC_MIXED) continue;
+    const GramPlan& g = Ls[k].g;
+    prob_of[k] = (int)probs.size();
+    GramProb gp{};
+    gp.N = N[k];
+    gp.p = params[k].p;
+    gp.n = params[k].n;
+    gp.M = (int)Ms[k];
+    gp.T = g.T;
+    gp.chunk = g.chunk;
+    probs.push_back(gp);
+    lds = std::max(lds, gram_mixed_lds_bytes(params[k].p, params[k].n));
+    for (int sp = 0; sp < g.splits_total; ++sp)
+      for (int t = 0; t < g.ntiles; ++t)
+        for (int h = 0; h < 2; ++h) items.push_back(GramItem{prob_of[k], t, h, sp});
+  }
+  // longest first: full chunks before each problem's shorter last chunk
+  std::stable_sort(items.begin(), items.end(), [&](const GramItem& a, const GramItem& b) {
+    auto len = [&](const GramItem& i) {
+      const GramProb& q = probs[i.prob];
+      return std::min<int64_t>(q.chunk, q.N - (int64_t)i.split * q.chunk);
+    };
+    return len(a) > len(b);
+  });
+  const size_t meta = probs.size() * sizeof(GramProb) + items.size() * sizeof(GramItem) + 256;
+  char* ws = nullptr;
+  hipError_t e = hipMallocAsync((void**)&ws, total + meta + 512, s);
+  if (e != hipSuccess) {
+    for (auto* m : ms) model_release(m, s, true);
+    return fail(GP_ENOMEM, "batch workspace of %zu bytes", total + meta);
+  }
+  for (int k = 0; k < count; ++k)
+    if (prob_of[k] >= 0) {
+      probs[prob_of[k]].tab32 = (const float*)(ws + off[k] + Ls[k].tab32);
+      probs[prob_of[k]].part = (float*)(ws + off[k] + Ls[k].gpart);
+    }
+  GramProb* probs_dev = (GramProb*)(ws + total);
+  GramItem* items_dev = (GramItem*)((char*)probs_dev + ((probs.size() * sizeof(GramProb) + 255) & ~(size_t)255));
+  int* counter = (int*)((char*)items_dev + ((items.size() * sizeof(GramItem) + 255) & ~(size_t)255));
+  if (!probs.empty()) {
+    hipMemcpyAsync(probs_dev, probs.data(), probs.size() * sizeof(GramProb), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(items_dev, items.data(), items.size() * sizeof(GramItem), hipMemcpyHostToDevice, s);
+  }
+  // capture: cs forks to kForks streams for the per-problem head and tail
+  constexpr int kForks = 4;
+  hipStream_t cs, fs[kForks];
+  hipEvent_t ev_start, ev_fork, ev_join[kForks], ev_heads[kForks], ev_done;
+  hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  for (int f = 0; f < kForks; ++f) {
+    hipStreamCreateWithFlags(&fs[f], hipStreamNonBlocking);
+    hipEventCreateWithFlags(&ev_join[f], hipEventDisableTiming);
+    hipEventCreateWithFlags(&ev_heads[f], hipEventDisableTiming);
+  }
+  hipEventCreateWithFlags(&ev_start, hipEventDisableTiming);
+  hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+  hipEventCreateWithFlags(&ev_done, hipEventDisableTiming);
+  hipEventRecord(ev_start, s);
+  hipStreamWaitEvent(cs, ev_start, 0);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    // heads on the forks
+    hipEventRecord(ev_fork, cs);
+    for (int f = 0; f < kForks; ++f) hipStreamWaitEvent(fs[f], ev_fork, 0);
+    for (int k = 0; k < count; ++k)
+      enqueue_fit_head(ms[k], x[k], y[k], N[k], Ls[k], ws + off[k], fs[k % kForks]);
+    for (int f = 0; f < kForks; ++f) {
+      hipEventRecord(ev_heads[f], fs[f]);
+      hipStreamWaitEvent(cs, ev_heads[f], 0);
+    }
+    // one persistent Gram launch for all mixed problems
+    if (!items.empty()) launch_gram_mixed_batch(probs_dev, items_dev, (int)items.size(), counter, lds, cs, nullptr);
+    hipEventRecord(ev_fork, cs);
+    for (int f = 0; f < kForks; ++f) hipStreamWaitEvent(fs[f], ev_fork, 0);
+    for (int k = 0; k < count; ++k) {
+      gp_model* m = ms[k];
+      hipStream_t fk = fs[k % kForks];
+      const int M = (int)Ms[k];
+      if (params[k].precision == GP_PREC_MIXED) {
+        launch_gram_mixed_reduce((const float*)(ws + off[k] + Ls[k].gpart), Ls[k].g.splits_total, Ls[k].g.T, M,
+                                 m->reg, true, m->A, fk);
+      } else {
+        launch_gram_f64(x[k], N[k], params[k].p, params[k].n, M, m->tab, m->reg, (double*)(ws + off[k] + Ls[k].gpart),
+                        m->A, fk, nullptr);
+      }
+      enqueue_fit_tail(m, x[k], y[k], N[k], Ls[k], ws + off[k], fk);
+    }
+    for (int f = 0; f < kForks; ++f) {
+      hipEventRecord(ev_join[f], fs[f]);
+      hipStreamWaitEvent(cs, ev_join[f], 0);
+    }
+    e = hipStreamEndCapture(cs, &graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(exec, cs);
+  hipEventRecord(ev_done, cs);
+  hipStreamWaitEvent(s, ev_done, 0);
+  std::vector<int> flags(2 * count, 0);
+  if (e == hipSuccess) {
+    for (int k = 0; k < count; ++k)
+      hipMemcpyAsync(&flags[2 * k], ms[k]->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+    e = hipStreamSynchronize(s);
+  }
+  hipFreeAsync(ws, s);
+  hipStreamSynchronize(s);
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  for (int f = 0; f < kForks; ++f) {
+    hipStreamDestroy(fs[f]);
+    hipEventDestroy(ev_join[f]);
+    hipEventDestroy(ev_heads[f]);
+  }
+  hipStreamDestroy(cs);
+  hipEventDestroy(ev_start);
+  hipEventDestroy(ev_fork);
+  hipEventDestroy(ev_done);
+  if (e != hipSuccess) {
+    for (auto* m : ms) model_release(m, nullptr, true);
+    return fail(GP_EDEVICE, "gp_fit_batch: %s", hipGetErrorString(e));
+  }
+  gp_status result = GP_OK;
+  for (int k = 0; k < count; ++k) {
+    if (flags[2 * k + 1] || flags[2 * k]) {
+      if (result == GP_OK)
+        result = flags[2 * k + 1] ? fail(GP_EINVAL, "problem %d: x or y holds a non-finite value", k)
+                                  : fail(GP_ENOTSPD, "problem %d: Cholesky pivot at column %d", k, flags[2 * k] - 1);
+      model_release(ms[k], nullptr, true);
+      ms[k] = nullptr;
+    }
+    out_models[k] = ms[k];
+  }
+  return result;
+}
+
+gp_status gp_predict_batch(gp_ctx* ctx, int32_t count, const gp_model* const* models, const double* const* xs,
+                           const int64_t* Ns, double* const* mean, double* const* var, void* stream) {
+  if (!ctx || count < 0 || (count > 0 && (!models || !xs || !Ns)))
+    return fail(GP_EINVAL, "gp_predict_batch: NULL argument or negative count");
+  if (count == 0) return GP_OK;
+  std::vector<size_t> off(count);
+  size_t total = 0;
+  for (int k = 0; k < count; ++k) {
+    if (!models[k] || Ns[k] < 0 || (Ns[k] > 0 && !xs[k])) return fail(GP_EINVAL, "problem %d: bad arguments", k);
+    off[k] = total;
+    total += (predict_workspace_bytes(Ns[k], models[k]->M, models[k]->precision) + 255) & ~(size_t)255;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(GP_EDEVICE, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = nullptr;
+  if (hipMallocAsync((void**)&ws, total + 256, s) != hipSuccess) return fail(GP_ENOMEM, "predict batch workspace");
+  constexpr int kForks = 4;
+  hipStream_t fs[kForks];
+  hipEvent_t ev_fork, ev_join[kForks];
+  hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+  hipEventRecord(ev_fork, s);
+  for (int f = 0; f < kForks; ++f) {
+    hipStreamCreateWithFlags(&fs[f], hipStreamNonBlocking);
+    hipEventCreateWithFlags(&ev_join[f], hipEventDisableTiming);
+    hipStreamWaitEvent(fs[f], ev_fork, 0);
+  }
+  for (int k = 0; k < count; ++k)
+    enqueue_predict(models[k], xs[k], Ns[k], mean ? mean[k] : nullptr, var ? var[k] : nullptr, ws + off[k],
+                    fs[k % kForks]);
+  for (int f = 0; f < kForks; ++f) {
+    hipEventRecord(ev_join[f], fs[f]);
+    hipStreamWaitEvent(s, ev_join[f], 0);
+  }
+  hipFreeAsync(ws, s);
+  for (int f = 0; f < kForks; ++f) {
+    hipStreamDestroy(fs[f]);
+    hipEventDestroy(ev_join[f]);
+  }
+  hipEventDestroy(ev_fork);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GP_EDEVICE, "gp_predict_batch: %s", hipGetErrorString(e));
+  return GP_OK;
+}
+
+}  // extern "C"

@@ -467,7 +467,7 @@ size_t trtri_workspace_elems(int M) {
 
 void launch_trtri(const double* L, const double* Dinv, double* Linv, double* ws, int M, const int* info,
                   hipStream_t s) {
-  hipMemsetAsync(Linv, 0, (size_t)M * M * sizeof(double), s);
+  launch_fill_zero_f64(Linv, (int64_t)M * M, s);
   const int nblk = (int)ceil_div(M, kNb);
   hipLaunchKernelGGL(trtri_diag_kernel, dim3(nblk), dim3(256), 0, s, Dinv, Linv, M);
   for (int b = kNb; b < M; b *= 2) {

@@ -34,12 +34,35 @@ void launch_gram_f64(const double* x, int64_t N, int p, int n, int M, const doub
                      const double* reg, double* part, double* A, hipStream_t s, Prof* prof = nullptr);
 
 // a3 (mixed): split-BF16 MFMA Gram, FP32 accumulate, FP64 split-K reduce.
-// tab32 holds gram_mixed_table_elems() floats of workspace (1-D tables).
-int64_t gram_mixed_part_elems(int64_t N, int M, int* splitk_out);
+// Samples are processed in chunks of `chunk` (a multiple of 16); each
+// (upper tile, chunk) writes an FP32 partial, at most ~4 GB of partials per
+// pass.  tab32 holds gram_mixed_table_elems() floats (1-D tables).
+struct GramPlan {
+  int T, ntiles, chunk, splits_total, splits_per_pass, passes;
+};
+GramPlan gram_mixed_plan(int64_t N, int M, int chunk /* <= 0: default */);
+int64_t gram_mixed_part_elems(const GramPlan& g);
 int64_t gram_mixed_table_elems(int64_t N, int p, int n);
-void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const double* tab,
-                       const double* reg, float* part, float* tab32, double* A, hipStream_t s,
-                       Prof* prof = nullptr);
+size_t gram_mixed_lds_bytes(int p, int n);
+void launch_gram_mixed_table(const double* x, int64_t N, int p, int n, const double* tab, float* tab32,
+                             hipStream_t s);
+void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const GramPlan& g,
+                       const double* tab, const double* reg, float* part, float* tab32, double* A,
+                       hipStream_t s, Prof* prof = nullptr);
+void launch_gram_mixed_reduce(const float* part, int splits, int T, int M, const double* reg,
+                              bool first, double* A, hipStream_t s);
+// Batched: one persistent launch over the work items of many problems.
+struct GramProb {
+  const float* tab32;
+  float* part;
+  int64_t N;
+  int p, n, M, T, chunk, pad;
+};
+struct GramItem {
+  int prob, tile, h, split;
+};
+void launch_gram_mixed_batch(const GramProb* probs_dev, const GramItem* items_dev, int nitems,
+                             int* counter, size_t lds, hipStream_t s, Prof* prof = nullptr);
 
 // a4: blocked Cholesky in place (lower), block inverses Dinv[M/64][64*64],
 // info (device int, 0 = ok, else failing column + 1).
@@ -71,6 +94,10 @@ int64_t predict_mixed_part_elems(int64_t Ns, int M, int* groups_out);
 void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, const double* tab,
                           const __bf16* linv_pieces, const double* w, double sigma2, double* part,
                           double* mean, double* var, hipStream_t s, Prof* prof = nullptr);
+
+// Zero fills as kernels (safe inside captured graphs).
+void launch_fill_zero_int(int* p, int count, hipStream_t s);
+void launch_fill_zero_f64(double* p, int64_t count, hipStream_t s);
 
 // Device check that every element of v[count] is finite; sets *flag = 1 if not.
 void launch_check_finite(const double* v, int64_t count, int* flag, hipStream_t s);

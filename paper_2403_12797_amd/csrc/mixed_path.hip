@@ -98,15 +98,17 @@ constexpr int kGmChunk = 8192;                              // samples per FP32 
 constexpr int64_t kGmPartCap = 4ll << 30;                   // bytes of partials per pass
 constexpr int kGmStageElems = 3 * kG2Slots * kG2SlotPitch;  // bf16 per stage buffer
 
-struct GramPlan {
-  int T, ntiles, splits_total, splits_per_pass, passes;
-};
-
-static GramPlan gram_mixed_plan(int64_t N, int M) {
+GramPlan gram_mixed_plan(int64_t N, int M, int chunk) {
   GramPlan g;
   g.T = (int)ceil_div(M, kGmT);
   g.ntiles = g.T * (g.T + 1) / 2;
-  g.splits_total = (int)ceil_div(N, kGmChunk);
+  if (chunk <= 0) {
+    // enough work items to fill the GPU several times over: chunks of 1024..8192 samples
+    const int64_t want = ceil_div(N * 2 * g.ntiles, 1024);
+    chunk = (int)std::min<int64_t>(kGmChunk, std::max<int64_t>(1024, ceil_div(want, kGmKC) * kGmKC));
+  }
+  g.chunk = (int)ceil_div(chunk, kGmKC) * kGmKC;
+  g.splits_total = (int)ceil_div(N, g.chunk);
   const int64_t per_split = (int64_t)g.ntiles * kGmT * kGmT * sizeof(float);
   int64_t sp = kGmPartCap / per_split;
   if (sp < 1) sp = 1;
@@ -116,11 +118,7 @@ static GramPlan gram_mixed_plan(int64_t N, int M) {
   return g;
 }
 
-int64_t gram_mixed_part_elems(int64_t N, int M, int* splitk_out) {
-  const GramPlan g = gram_mixed_plan(N, M);
-  if (splitk_out) *splitk_out = g.splits_per_pass;
-  return (int64_t)g.splits_per_pass * g.ntiles * kGmT * kGmT;
-}
+int64_t gram_mixed_part_elems(const GramPlan& g) { return (int64_t)g.splits_per_pass * g.ntiles * kGmT * kGmT; }
 
 // Three zero stages past the end let the kernel prefetch without bounds tests.
 int64_t gram_mixed_table_elems(int64_t N, int p, int n) { return (ceil_div(N, kGmKC) + 3) * p * n * kGmKC; }
@@ -154,11 +152,12 @@ __device__ __forceinline__ void gm_store3(const float* v, __bf16* __restrict__ s
   }
 }
 
-template <int P>
-__global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __restrict__ tab32, int64_t N,
-                                                                   int n, int M, int T, int split0,
-                                                                   float* __restrict__ part) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smraw[];
+// One work item: tile `tile` (upper-triangle index), half h, samples
+// [r0, r0 + chunk) of a problem; writes the item's FP32 partial 256x256 tile
+// (half h) at `out`.
+__device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __restrict__ tab32, int64_t N, int P,
+                                          int n, int M, int T, int tile, int h, int64_t r0, int chunk,
+                                          float* __restrict__ out) {
   // LDS: two stage buffers of split Phi, three 1-D table buffers, two prefix
   // buffers.  Addressed as base + offset so the compiler keeps them in LDS.
   __bf16* const stg0 = reinterpret_cast<__bf16*>(smraw);
@@ -169,8 +168,7 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __r
   const int prs = gm_pre_rows(n) * kG2TabPitch; // floats per prefix buffer
   const int tchunks = rows * (kGmKC / 4);       // float4 per stage of the table
 
-  int tile = blockIdx.x >> 1, I = 0;
-  const int h = blockIdx.x & 1;
+  int I = 0;
   while (tile >= T - I) {
     tile -= T - I;
     ++I;
@@ -210,8 +208,7 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __r
         sum[a][b][r] = 0.0f;
       }
 
-  const int64_t r0 = (int64_t)(split0 + blockIdx.y) * kGmChunk;
-  int64_t r1 = r0 + kGmChunk;
+  int64_t r1 = r0 + chunk;
   if (r1 > N) r1 = N;
   const int nst = (int)ceil_div(r1 - r0, kGmKC);
   const int64_t st0 = r0 / kGmKC;
@@ -238,7 +235,6 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __r
       float4 v = float4{1.f, 1.f, 1.f, 1.f};
       if (hi >= 0) {
         int rem = hi;
-#pragma unroll
         for (int j = P - 2; j >= 0; --j) {
           const float4 f = *reinterpret_cast<const float4*>(Tb + (j * n + rem % n) * kG2TabPitch + q4);
           v.x *= f.x;
@@ -357,8 +353,6 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __r
         }
   }
 
-  const int ntiles = T * (T + 1) / 2;
-  float* out = part + ((int64_t)blockIdx.y * ntiles + (blockIdx.x >> 1)) * (kGmT * kGmT);
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -371,22 +365,45 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __r
       }
 }
 
-typedef void (*GramKernel)(const float*, int64_t, int, int, int, int, float*);
-static GramKernel gram_kernel_for(int p) {
-  switch (p) {
-    case 1: return gram_mixed_kernel<1>;
-    case 2: return gram_mixed_kernel<2>;
-    case 3: return gram_mixed_kernel<3>;
-    case 4: return gram_mixed_kernel<4>;
-    case 5: return gram_mixed_kernel<5>;
-    case 6: return gram_mixed_kernel<6>;
-    case 7: return gram_mixed_kernel<7>;
-    default: return gram_mixed_kernel<8>;
+// A (+)= sum of the pass's FP32 partials in split order (FP64); the first pass
+// also adds reg on the diagonal.  Writes both triangles.
+// Single problem: grid (2 * ntiles, splits of this pass).
+__global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __restrict__ tab32, int64_t N, int p,
+                                                                int n, int M, int T, int split0, int chunk,
+                                                                float* __restrict__ part) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smraw[];
+  const int ntiles = T * (T + 1) / 2;
+  const int tile = blockIdx.x >> 1;
+  float* out = part + ((int64_t)blockIdx.y * ntiles + tile) * (kGmT * kGmT);
+  gram_item(smraw, tab32, N, p, n, M, T, tile, blockIdx.x & 1, (int64_t)(split0 + blockIdx.y) * chunk, chunk, out);
+}
+
+// Many problems in one persistent launch: work-groups take items from a
+// longest-first list through an atomic counter until it runs out.
+__global__ void __launch_bounds__(kG2Threads) gram_mixed_batch_kernel(const GramProb* __restrict__ probs,
+                                                                      const GramItem* __restrict__ items, int nitems,
+                                                                      int* __restrict__ counter) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smraw[];
+  __shared__ int next;
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = next;
+    if (it >= nitems) break;
+    const GramItem wi = items[it];
+    const GramProb pr = probs[wi.prob];
+    const int ntiles = pr.T * (pr.T + 1) / 2;
+    float* out = pr.part + ((int64_t)wi.split * ntiles + wi.tile) * (kGmT * kGmT);
+    gram_item(smraw, pr.tab32, pr.N, pr.p, pr.n, pr.M, pr.T, wi.tile, wi.h, (int64_t)wi.split * pr.chunk, pr.chunk,
+              out);
   }
 }
 
-// A (+)= sum of the pass's FP32 partials in split order (FP64); the first pass
-// also adds reg on the diagonal.  Writes both triangles.
+__global__ void reset_counter_kernel(int* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+}
+
 __global__ void gram_mixed_reduce_kernel(const float* __restrict__ part, int splits, int T, int M,
                                          const double* __restrict__ reg, int first, double* __restrict__ A) {
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
@@ -402,27 +419,49 @@ __global__ void gram_mixed_reduce_kernel(const float* __restrict__ part, int spl
   A[(int64_t)h * M + g] = s;
 }
 
-void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const double* tab, const double* reg,
-                       float* part, float* tab32, double* A, hipStream_t s, Prof* prof) {
-  const GramPlan g = gram_mixed_plan(N, M);
+size_t gram_mixed_lds_bytes(int p, int n) { return gram_lds_bytes(p, n); }
+
+void launch_gram_mixed_table(const double* x, int64_t N, int p, int n, const double* tab, float* tab32,
+                             hipStream_t s) {
   const int64_t nstage = ceil_div(N, kGmKC) + 3;
-  const size_t lds = gram_lds_bytes(p, n);
-  prof_mark(prof, GP_PH_GRAM, true, s);
   hipLaunchKernelGGL(phi1d_table_kernel, dim3(ceil_div(nstage * p * kGmKC, 256)), dim3(256), 0, s, x, N, p, n, tab,
                      tab32, nstage);
+}
+
+void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const GramPlan& g, const double* tab,
+                       const double* reg, float* part, float* tab32, double* A, hipStream_t s, Prof* prof) {
+  prof_mark(prof, GP_PH_GRAM, true, s);
+  launch_gram_mixed_table(x, N, p, n, tab, tab32, s);
   prof_mark(prof, GP_PH_GRAM, false, s);
   for (int ps = 0; ps < g.passes; ++ps) {
     const int split0 = ps * g.splits_per_pass;
     const int cnt = std::min(g.splits_per_pass, g.splits_total - split0);
     prof_mark(prof, GP_PH_GRAM, true, s);
-    hipLaunchKernelGGL(gram_kernel_for(p), dim3(2 * g.ntiles, cnt), dim3(kG2Threads), lds, s, tab32, N, n, M, g.T,
-                       split0, part);
+    hipLaunchKernelGGL(gram_mixed_kernel, dim3(2 * g.ntiles, cnt), dim3(kG2Threads), gram_lds_bytes(p, n), s, tab32,
+                       N, p, n, M, g.T, split0, g.chunk, part);
     prof_mark(prof, GP_PH_GRAM, false, s);
     prof_mark(prof, GP_PH_GRAM_REDUCE, true, s);
-    hipLaunchKernelGGL(gram_mixed_reduce_kernel, dim3(ceil_div(M, 256), M), dim3(256), 0, s, part, cnt, g.T, M,
-                       reg, ps == 0 ? 1 : 0, A);
+    launch_gram_mixed_reduce(part, cnt, g.T, M, reg, ps == 0, A, s);
     prof_mark(prof, GP_PH_GRAM_REDUCE, false, s);
   }
+}
+
+void launch_gram_mixed_reduce(const float* part, int splits, int T, int M, const double* reg, bool first, double* A,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(gram_mixed_reduce_kernel, dim3(ceil_div(M, 256), M), dim3(256), 0, s, part, splits, T, M, reg,
+                     first ? 1 : 0, A);
+}
+
+void launch_gram_mixed_batch(const GramProb* probs_dev, const GramItem* items_dev, int nitems, int* counter,
+                             size_t lds, hipStream_t s, Prof* prof) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int grid = std::max(1, std::min(nitems, cus));
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
+  prof_mark(prof, GP_PH_GRAM, true, s);
+  hipLaunchKernelGGL(gram_mixed_batch_kernel, dim3(grid), dim3(kG2Threads), lds, s, probs_dev, items_dev, nitems,
+                     counter);
+  prof_mark(prof, GP_PH_GRAM, false, s);
 }
 
 // ================================================================ L^-1 split
@@ -733,10 +772,10 @@ namespace mgp {
 hipError_t configure_kernels() {
   const int big = 160 * 1024;
   hipError_t e = hipSuccess;
-  for (int p = 1; p <= GP_MAX_P; ++p) {
-    e = hipFuncSetAttribute((const void*)gram_kernel_for(p), hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    if (e != hipSuccess) return e;
-  }
+  e = hipFuncSetAttribute((const void*)gram_mixed_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)gram_mixed_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)predict_var_mixed_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)predict_var_mixed_kernel<128>, hipFuncAttributeMaxDynamicSharedMemorySize, big);

@@ -84,13 +84,34 @@ struct gp_ctx {
   std::thread thread;
   // fault injection: names of failures to report for the next request(s)
   std::string faults;
+  // autotuned Gram chunk lengths: key (p, n, floor(log2 N)) -> chunk
+  std::mutex tune_mu;
+  std::map<int64_t, int> tune;
+  std::string tune_path;
 };
+
+#include "kernels.h"
 
 namespace mgp {
 gp_status fail(gp_status st, const char* fmt, ...);
+// Transient device memory of a fit: one block carved into these arrays
+// (byte offsets).  all_splits keeps every Gram partial (no passes).
+struct FitLayout {
+  GramPlan g;
+  size_t gpart, tab32, vpart, resid, z, r, d, ltpart, trws, total;
+};
+FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chunk, bool all_splits);
+void enqueue_fit_head(gp_model* m, const double* x, const double* y, int64_t N, const FitLayout& L, void* ws,
+                      hipStream_t s);
+void enqueue_fit_tail(gp_model* m, const double* x, const double* y, int64_t N, const FitLayout& L, void* ws,
+                      hipStream_t s);
+void tune_load(gp_ctx* ctx);
 gp_status validate_params(const gp_params* prm, int64_t* M_out);
 size_t model_bytes(int64_t M, int precision);
-size_t fit_workspace_bytes(int64_t N, int p, int n, int64_t M, int precision);
+size_t fit_workspace_bytes(gp_ctx* ctx, int64_t N, int p, int n, int64_t M, int precision);
+// Gram chunk length chosen by the autotuner for (p, n, N) on this context,
+// 0 if none (the planner's default applies).
+int tuned_chunk(gp_ctx* ctx, int p, int n, int64_t N);
 size_t predict_workspace_bytes(int64_t Ns, int64_t M, int precision);
 gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t s, gp_model** out);
 // Free a model's device memory stream-ordered on s (after a device-wide sync

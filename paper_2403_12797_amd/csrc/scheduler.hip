@@ -78,7 +78,7 @@ static void launch(gp_ctx* ctx, Request* r, int k) {
   if (d.kind != GP_REQ_FIT && d.Ns > 0 && (d.mean || d.var)) {
     // predict workspace follows the fit workspace in the same block
     const size_t fitb =
-        d.kind == GP_REQ_FIT_PREDICT ? fit_workspace_bytes(d.N, pm->p, pm->n, pm->M, pm->precision) : 0;
+        d.kind == GP_REQ_FIT_PREDICT ? fit_workspace_bytes(ctx, d.N, pm->p, pm->n, pm->M, pm->precision) : 0;
     enqueue_predict(pm, d.xs, d.Ns, d.mean, d.var, (char*)r->ws + ((fitb + 255) & ~(size_t)255), sl.stream);
   }
   hipEventRecord(sl.done, sl.stream);
@@ -232,7 +232,7 @@ gp_status gp_submit(gp_ctx* ctx, const gp_request* req, int64_t* req_id) {
   }
   size_t ws = 0, foot = 0;
   if (req->kind != GP_REQ_PREDICT) {
-    ws += (fit_workspace_bytes(req->N, req->params.p, req->params.n, M, prec) + 255) & ~(size_t)255;
+    ws += (fit_workspace_bytes(ctx, req->N, req->params.p, req->params.n, M, prec) + 255) & ~(size_t)255;
     foot += model_bytes(M, prec);
   }
   if (req->kind != GP_REQ_FIT) ws += predict_workspace_bytes(req->Ns, M, prec);

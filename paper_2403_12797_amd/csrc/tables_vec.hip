@@ -148,46 +148,116 @@ void launch_phi_matvec(const double* x, int64_t N, int p, int n, int M, const do
 }
 
 // ---------------------------------------------------------------- Phi^T v
-// Grid (column blocks of 256, sample chunks of kTvChunk).  Thread = column;
-// the table is column-fastest so lanes (consecutive columns) read distinct
-// or broadcast LDS words.  Partials part[chunk][M] are reduced in chunk order.
-constexpr int kTvChunk = 2048;
-constexpr int kTvSub = 32;
+// With m = hi*n + k (k the last digit), Phi[i, m] = PRE[i][hi] * phi_{p-1,k}(x_i)
+// where PRE is the product of the leading p-1 factors, so
+//   (Phi^T v)[hi*n + k] = sum_i PRE[i][hi] * (phi_{p-1,k}(x_i) v_i),
+// an (M/n x N) by (N x n) product.  Work-group: 256 prefixes hi x all n
+// last digits over a chunk of kTvChunk samples, FP64 MFMA (16x16x4) on
+// per-stage tiles of 16 samples built in LDS: PRE^T [16 samples][256 hi]
+// and W [16 samples][n padded to 16].  Partials part[chunk][M] are reduced
+// in chunk order.
+constexpr int kTvChunk = 1024;
+constexpr int kTvKC = 16;
+constexpr int kTvH = 256;
+
+__device__ __forceinline__ f64x4 mfma64v(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 int64_t phiT_part_elems(int64_t N, int M) { return ceil_div(N, kTvChunk) * (int64_t)M; }
 
-__global__ void __launch_bounds__(256) phiT_part_kernel(const double* __restrict__ x,
-                                                        const double* __restrict__ v, int64_t N, int p,
-                                                        int n, int M, const double* __restrict__ tab,
-                                                        double* __restrict__ part) {
+template <int NB>   // NB = ceil(n / 16) column blocks of the last digit
+__global__ void __launch_bounds__(256) phiT_gemm_kernel(const double* __restrict__ x, const double* __restrict__ v,
+                                                        int64_t N, int p, int n, int M,
+                                                        const double* __restrict__ tab, double* __restrict__ part) {
   extern __shared__ double sm[];
-  const int ld = p * n + 1;
-  double* T = sm;                      // [kTvSub][ld]
-  double* V = sm + kTvSub * ld;        // [kTvSub]
-  const int m = blockIdx.x * 256 + threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.y * kTvChunk;
-  int off[GP_MAX_P];
+  double* T = sm;                                 // [p*n][16] 1-D tables of the stage
+  double* PR = T + p * n * kTvKC;                 // [16][kTvH + 2]
+  double* W = PR + kTvKC * (kTvH + 2);            // [16][NB*16 + 2]
+  const int WP = NB * 16 + 2;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int H = M / n;
+  const int h0 = blockIdx.y * kTvH;
+  const int64_t c0 = (int64_t)blockIdx.x * kTvChunk;
+  const int64_t c1 = min(c0 + kTvChunk, N);
+  // prefix digits of this thread's hi (one per thread)
+  const int hi = h0 + t;
+  int dig[GP_MAX_P];
   {
-    int rem = m < M ? m : 0;
-    for (int j = p - 1; j >= 0; --j) {
-      off[j] = j * n + rem % n;
+    int rem = hi < H ? hi : 0;
+    for (int j = p - 2; j >= 0; --j) {
+      dig[j] = rem % n;
       rem /= n;
     }
   }
-  double acc = 0.0;
-  for (int64_t s0 = c0; s0 < c0 + kTvChunk && s0 < N; s0 += kTvSub) {
+  f64x4 acc[4][NB];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  for (int64_t s0 = c0; s0 < c1; s0 += kTvKC) {
     __syncthreads();
-    fill_tab_cf(x, N, p, n, s0, kTvSub, ld, tab, T);
-    if (threadIdx.x < kTvSub) V[threadIdx.x] = (s0 + threadIdx.x < N) ? v[s0 + threadIdx.x] : 0.0;
+    // 1-D tables: thread (i, j) for i < 16, j < p
+    if (t < kTvKC * p) {
+      const int i = t % kTvKC, j = t / kTvKC;
+      const int64_t row = s0 + i;
+      double* o = T + (j * n) * kTvKC + i;
+      if (row < c1) {
+        const double* dc = tab + kTabDim + j * kDimStride;
+        phi_1d<double, double>(x[row * p + j], dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, kTvKC);
+      } else {
+        for (int k = 0; k < n; ++k) o[k * kTvKC] = 0.0;
+      }
+    }
     __syncthreads();
-    for (int i = 0; i < kTvSub; ++i) {
-      const double* Ti = T + i * ld;
-      double ph = Ti[off[0]];
-      for (int j = 1; j < p; ++j) ph *= Ti[off[j]];
-      acc = fma(ph, V[i], acc);
+    // PRE^T: thread = prefix, 16 samples
+    {
+      double pr[kTvKC];
+#pragma unroll
+      for (int i = 0; i < kTvKC; ++i) pr[i] = (hi < H) ? 1.0 : 0.0;
+      for (int j = 0; j < p - 1; ++j) {
+        const double* Tj = T + (j * n + dig[j]) * kTvKC;
+#pragma unroll
+        for (int i = 0; i < kTvKC; ++i) pr[i] *= Tj[i];
+      }
+#pragma unroll
+      for (int i = 0; i < kTvKC; ++i) PR[i * (kTvH + 2) + t] = pr[i];
+    }
+    // W = last-dimension factor times v: [16][NB*16]
+    for (int u = t; u < kTvKC * NB * 16; u += 256) {
+      const int i = u / (NB * 16), k = u % (NB * 16);
+      const int64_t row = s0 + i;
+      W[i * WP + k] = (k < n && row < c1) ? T[((p - 1) * n + k) * kTvKC + i] * v[row] : 0.0;
+    }
+    __syncthreads();
+    // MFMA: wave wv owns prefixes wv*64 .. +64 (4 blocks of 16)
+#pragma unroll
+    for (int kk = 0; kk < kTvKC / 4; ++kk) {
+      const int i = kk * 4 + (lane >> 4);
+      double av[4], bv[NB];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = PR[i * (kTvH + 2) + wv * 64 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[b] = W[i * WP + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = mfma64v(av[a], bv[b], acc[a][b]);
     }
   }
-  if (m < M) part[blockIdx.y * (int64_t)M + m] = acc;
+  // D[hi][k]: element q of acc[a][b] is row 4q + lane/16, column lane%16
+  double* out = part + (int64_t)blockIdx.x * M;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int h = h0 + wv * 64 + a * 16 + 4 * q + (lane >> 4);
+        const int k = b * 16 + (lane & 15);
+        if (h < H && k < n) out[(int64_t)h * n + k] = acc[a][b][q];
+      }
 }
 
 __global__ void reduce_cols_kernel(const double* __restrict__ part, int64_t chunks, int M,
@@ -204,12 +274,17 @@ __global__ void reduce_cols_kernel(const double* __restrict__ part, int64_t chun
 void launch_phiT_vec(const double* x, const double* v, int64_t N, int p, int n, int M, const double* tab,
                      double* part, const double* sub, const double* wsub, double* out, hipStream_t s) {
   const int64_t chunks = ceil_div(N, kTvChunk);
-  const int ld = p * n + 1;
-  const size_t lds = (size_t)(kTvSub * ld + kTvSub) * sizeof(double);
-  hipLaunchKernelGGL(phiT_part_kernel, dim3(ceil_div(M, 256), chunks), dim3(256), lds, s, x, v, N, p, n, M,
-                     tab, part);
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part, chunks, M, sub, wsub,
-                     out);
+  const int H = M / n;
+  const int NB = (int)ceil_div(n, 16);
+  const size_t lds = (size_t)(p * n * kTvKC + kTvKC * (kTvH + 2) + kTvKC * (NB * 16 + 2)) * sizeof(double);
+  const dim3 grid(chunks, ceil_div(H, kTvH));
+  switch (NB) {
+    case 1: hipLaunchKernelGGL(phiT_gemm_kernel<1>, grid, dim3(256), lds, s, x, v, N, p, n, M, tab, part); break;
+    case 2: hipLaunchKernelGGL(phiT_gemm_kernel<2>, grid, dim3(256), lds, s, x, v, N, p, n, M, tab, part); break;
+    case 3: hipLaunchKernelGGL(phiT_gemm_kernel<3>, grid, dim3(256), lds, s, x, v, N, p, n, M, tab, part); break;
+    default: hipLaunchKernelGGL(phiT_gemm_kernel<4>, grid, dim3(256), lds, s, x, v, N, p, n, M, tab, part); break;
+  }
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part, chunks, M, sub, wsub, out);
 }
 
 // ---------------------------------------------------------------- input checks
@@ -225,6 +300,25 @@ void launch_check_finite(const double* v, int64_t count, int* flag, hipStream_t 
   int64_t blocks = ceil_div(count, 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(check_finite_kernel, dim3(blocks), dim3(256), 0, s, v, count, flag);
+}
+
+// ---------------------------------------------------------------- fills (kernels, not memset nodes)
+__global__ void fill_zero_int_kernel(int* __restrict__ p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+__global__ void fill_zero_f64_kernel(double* __restrict__ p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+void launch_fill_zero_int(int* p, int count, hipStream_t s) {
+  hipLaunchKernelGGL(fill_zero_int_kernel, dim3(ceil_div(count, 256)), dim3(256), 0, s, p, count);
+}
+void launch_fill_zero_f64(double* p, int64_t count, hipStream_t s) {
+  int64_t blocks = ceil_div(count, 256);
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(fill_zero_f64_kernel, dim3(blocks), dim3(256), 0, s, p, count);
 }
 
 // ---------------------------------------------------------------- small vector ops

@@ -1,0 +1,114 @@
+"""Batched fit/predict (gp_fit_batch / gp_predict_batch, one persistent Gram
+launch for all mixed problems, captured graph) and the autotuner.
+
+* every batched result equals the same problem fitted alone (bitwise: the
+  batch uses the same per-problem chunking and reduction order);
+* a sample of problems matches the FP64 oracle within the mixed tolerances;
+* a failing problem (non-finite input) leaves the others intact.
+"""
+import numpy as np
+import pytest
+
+from oracle import mercer_gp as o
+from paper_2403_12797_amd import binding as B
+from paper_2403_12797_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+
+
+def batch_problems(count=24, N_max=20_000):
+    # the batched workload's distribution (p in 1..3, n in 4..12, log-uniform N) at oracle-friendly sizes
+    return wl.batched_problems(count, N_max=N_max)
+
+
+def single(ctx, torch, P, prec):
+    x, y, xs = dev(torch, P.x), dev(torch, P.y), dev(torch, P.xs)
+    m = ctx.fit(x, y, p=P.p, n=P.n, sigma=P.sigma, eps=P.eps, alpha=P.alpha, precision=prec)
+    mean = torch.empty(P.Ns, dtype=torch.float64, device="cuda")
+    var = torch.empty_like(mean)
+    ctx.predict(m, xs, mean, var)
+    torch.cuda.synchronize()
+    w = m.get(B.MODEL_W)
+    m.free()
+    return w, mean.cpu().numpy(), var.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [B.PREC_MIXED, B.PREC_FP64])
+def test_batch_equals_single_and_oracle(torch_cuda, prec):
+    torch = torch_cuda
+    Ps = batch_problems()
+    with B.Context(0) as ctx:
+        dx = [(dev(torch, P.x), dev(torch, P.y), P.p, P.n, P.sigma, P.eps, P.alpha) for P in Ps]
+        models = ctx.fit_batch(dx, precision=prec)
+        xs = [dev(torch, P.xs) for P in Ps]
+        means = [torch.empty(P.Ns, dtype=torch.float64, device="cuda") for P in Ps]
+        vars_ = [torch.empty(P.Ns, dtype=torch.float64, device="cuda") for P in Ps]
+        ctx.predict_batch(models, xs, means, vars_)
+        torch.cuda.synchronize()
+        for k, P in enumerate(Ps):
+            print(f"[case] batch {P.name} prec={prec} M={P.M}", flush=True)
+            w_s, m_s, v_s = single(ctx, torch, P, prec)
+            assert np.array_equal(models[k].get(B.MODEL_W), w_s)
+            assert np.array_equal(means[k].cpu().numpy(), m_s)
+            assert np.array_equal(vars_[k].cpu().numpy(), v_s)
+        for k in range(0, len(Ps), 6):
+            P = Ps[k]
+            f = o.fit(P.x, P.y, P.sigma, P.eps, P.alpha, P.n)
+            om, ov = o.predict(f, P.xs)
+            em, ev = rel(means[k].cpu().numpy(), om), rel(vars_[k].cpu().numpy(), ov)
+            print(f"[err] batch {P.name} prec={prec} mean={em:.3e} var={ev:.3e}", flush=True)
+            if prec == B.PREC_MIXED:
+                assert em <= 1e-5 and ev <= 1e-4
+            else:
+                assert em <= 1e-10 and ev <= 1e-10
+        for m in models:
+            m.free()
+
+
+def test_batch_failure_isolated(torch_cuda):
+    torch = torch_cuda
+    Ps = batch_problems(6)
+    with B.Context(0) as ctx:
+        dx = [(dev(torch, P.x), dev(torch, P.y), P.p, P.n, P.sigma, P.eps, P.alpha) for P in Ps]
+        bad = dx[2][0].clone()
+        bad[0, 0] = float("nan")
+        dx[2] = (bad,) + dx[2][1:]
+        with pytest.raises(B.GpError) as ei:
+            ctx.fit_batch(dx)
+        assert ei.value.status == B.GP_EINVAL and "problem 2" in str(ei.value)
+        models = ei.value.models
+        assert models[2] is None
+        for k in (0, 1, 3, 4, 5):
+            assert models[k] is not None
+            w = models[k].get(B.MODEL_W)
+            assert np.all(np.isfinite(w))
+            models[k].free()
+
+
+def test_autotune_then_fit(torch_cuda):
+    torch = torch_cuda
+    P = wl.random_problem(31, 3, 8, 40_000, 2_000)
+    with B.Context(0) as ctx:
+        chunk = ctx.autotune(P.p, P.n, P.N)
+        print(f"[case] autotune p=3 n=8 N=40000 -> chunk {chunk}", flush=True)
+        assert chunk % 16 == 0 and 1024 <= chunk <= 32768
+        w, mean, var = single(ctx, torch, P, B.PREC_MIXED)
+    f = o.fit(P.x, P.y, P.sigma, P.eps, P.alpha, P.n)
+    om, ov = o.predict(f, P.xs)
+    assert rel(mean, om) <= 1e-5 and rel(var, ov) <= 1e-4
