@@ -57,7 +57,8 @@ gp_status validate_params(const gp_params* prm, int64_t* M_out) {
 // Device bytes a fitted model holds (used by admission control too).
 size_t model_bytes(int64_t M, int precision) {
   const size_t MM = (size_t)M * M;
-  size_t b = kTabSize * 8 + 4 * M * 8 + 3 * MM * 8 + (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8 + 256;
+  size_t b = kTabSize * 8 + 4 * M * 8 + 3 * MM * 8 + (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8 +
+             (size_t)M * 16 + 512;
   if (precision == GP_PREC_MIXED) b += 2 * (size_t)M * linv_pitch((int)M) * 2;
   return b;
 }
@@ -147,7 +148,8 @@ gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t 
   const size_t MM = (size_t)M * M;
   const size_t sizes[] = {kTabSize * 8, (size_t)M * 8, (size_t)M * 8, MM * 8, MM * 8, MM * 8,
                           (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8, (size_t)M * 8, (size_t)M * 8,
-                          64, prm->precision == GP_PREC_MIXED ? 2 * (size_t)M * linv_pitch((int)M) * 2 : 0};
+                          64, prm->precision == GP_PREC_MIXED ? 2 * (size_t)M * linv_pitch((int)M) * 2 : 0,
+                          (size_t)M * 16};
   size_t total = 0;
   for (size_t s : sizes) total += align_up(s);
   hipError_t e = hipSetDevice(ctx->device);
@@ -176,6 +178,7 @@ gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t 
   m->b = (double*)take(sizes[8]);
   m->flags = (int*)take(sizes[9]);
   m->linv_pieces = prm->precision == GP_PREC_MIXED ? (__bf16*)take(sizes[10]) : nullptr;
+  m->midx = (uint16_t*)take(sizes[11]);
   *out = m;
   return GP_OK;
 }
@@ -199,6 +202,7 @@ void enqueue_fit_head(gp_model* m, const double* x, const double* y, int64_t N, 
   launch_check_finite(x, N * p, m->flags + 1, s);
   launch_check_finite(y, N, m->flags + 1, s);
   launch_eig_tables(a, m->tab, m->lam, m->reg, M, s);
+  launch_midx(p, n, M, m->midx, s);
   if (m->precision == GP_PREC_MIXED) launch_gram_mixed_table(x, N, p, n, m->tab, (float*)(wb + L.tab32), s);
 }
 
@@ -266,7 +270,7 @@ void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* me
   const double s2 = m->sigma * m->sigma;
   Prof* pr = &m->ctx->prof;
   if (m->precision == GP_PREC_MIXED) {
-    launch_predict_mixed(xs, Ns, p, n, M, m->tab, m->linv_pieces, m->w, s2, (double*)ws, mean, var, s, pr);
+    launch_predict_mixed(xs, Ns, p, n, M, m->tab, m->midx, m->linv_pieces, m->w, s2, (double*)ws, mean, var, s, pr);
   } else {
     if (mean) {
       prof_mark(pr, GP_PH_PREDICT_MEAN, true, s);

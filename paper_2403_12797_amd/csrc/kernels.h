@@ -92,8 +92,11 @@ void launch_predict_var_f64(const double* xs, int64_t Ns, int p, int n, int M, c
 // a5 mixed: fused mean (FP64 dot with w) and split-BF16 variance.
 int64_t predict_mixed_part_elems(int64_t Ns, int M, int* groups_out);
 void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, const double* tab,
-                          const __bf16* linv_pieces, const double* w, double sigma2, double* part,
-                          double* mean, double* var, hipStream_t s, Prof* prof = nullptr);
+                          const uint16_t* midx, const __bf16* linv_pieces, const double* w,
+                          double sigma2, double* part, double* mean, double* var, hipStream_t s,
+                          Prof* prof = nullptr);
+// Multi-index table: midx[c][j] = j*n + k_j(c), 8 uint16 per column.
+void launch_midx(int p, int n, int M, uint16_t* midx, hipStream_t s);
 
 // Zero fills as kernels (safe inside captured graphs).
 void launch_fill_zero_int(int* p, int count, hipStream_t s);

@@ -464,6 +464,30 @@ void launch_gram_mixed_batch(const GramProb* probs_dev, const GramItem* items_de
   prof_mark(prof, GP_PH_GRAM, false, s);
 }
 
+// ================================================================ multi-index table
+// midx[c][j] = j*n + k_j(c): the 1-D table row of column c's factor in
+// dimension j (C order), zero past p.  8 uint16 per column.
+__global__ void midx_kernel(int p, int n, int M, uint16_t* __restrict__ midx) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= M) return;
+  uint16_t d[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int rem = c;
+  for (int j = p - 1; j >= 0; --j) {
+    d[j] = (uint16_t)(j * n + rem % n);
+    rem /= n;
+  }
+  uint4 v;
+  v.x = d[0] | ((uint32_t)d[1] << 16);
+  v.y = d[2] | ((uint32_t)d[3] << 16);
+  v.z = d[4] | ((uint32_t)d[5] << 16);
+  v.w = d[6] | ((uint32_t)d[7] << 16);
+  reinterpret_cast<uint4*>(midx)[c] = v;
+}
+
+void launch_midx(int p, int n, int M, uint16_t* midx, hipStream_t s) {
+  hipLaunchKernelGGL(midx_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, p, n, M, midx);
+}
+
 // ================================================================ L^-1 split
 // pieces[0] = hi, pieces[1] = lo of L^-1 (row pitch P, padding zero), each
 // element first rounded to FP32.  One thread per pair of columns.
@@ -523,10 +547,12 @@ int64_t predict_mixed_part_elems(int64_t Ns, int M, int* groups_out) {
   return 2 * g * Ns;
 }
 
-template <int TN>
+template <int TN, int P>
 __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
-    const double* __restrict__ xs, int64_t Ns, int p, int n, int M, const double* __restrict__ tab,
-    const __bf16* __restrict__ lpieces, const double* __restrict__ w, int rpg, double* __restrict__ part) {
+    const double* __restrict__ xs, int64_t Ns, int n, int M, const double* __restrict__ tab,
+    const uint16_t* __restrict__ midx, const __bf16* __restrict__ lpieces, const double* __restrict__ w, int rpg,
+    double* __restrict__ part) {
+  constexpr int p = P;
   using C = PmCfg<TN>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smraw[];
   float* const Tf = reinterpret_cast<float*>(smraw);                                  // [p*n][TN]
@@ -539,8 +565,8 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   const int rb0 = blockIdx.y * rpg, rb1 = min(rb0 + rpg, RB);
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wp = wv % C::WP, wr = wv / C::WP;
-  const int P = linv_pitch(M);
-  const int64_t PP = (int64_t)M * P;
+  const int LP = linv_pitch(M);
+  const int64_t PP = (int64_t)M * LP;
 
   for (int u = t; u < TN * p; u += kPmThreads) {
     const int i = u % TN, j = u / TN;
@@ -554,8 +580,10 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   }
   for (int u = t; u < C::WR * TN; u += kPmThreads) ssw[u] = 0.0;
 
-  // generation role: point gp, columns gq*CPT .. +CPT of each stage
-  const int gp = t % TN, gq = t / TN;
+  // generation role: point gp, columns gq*CPT .. +CPT of each stage (gq is
+  // wave-uniform, so the column indices and table entries are scalar)
+  const int gp = t % TN;
+  const int gq = __builtin_amdgcn_readfirstlane(t / TN);
   double mean_acc = 0.0;
 
   // the (column block, stage) sequence of this work-group
@@ -566,26 +594,23 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     const int c0 = stage_c0(k) + gq * C::CPT;
     const int r0 = rb * kPmTR;
     float v[C::CPT];
-    int prev_hi = -1;
-    float pre = 0.0f;
 #pragma unroll
     for (int u = 0; u < C::CPT; ++u) {
+      // column c's multi-index table entry (wave-uniform): LDS row j*n + k_j per dimension
       const int c = c0 + u;
-      float ph = 0.0f;
-      if (c < M) {
-        const int hi = c / n;
-        if (hi != prev_hi) {  // wave-uniform: recompute the product over the leading dims
-          int rem = hi;
-          pre = 1.0f;
-          for (int j = p - 2; j >= 0; --j) {
-            pre *= Tf[(j * n + rem % n) * TN + gp];
-            rem /= n;
-          }
-          prev_hi = hi;
-        }
-        ph = pre * Tf[((p - 1) * n + (c - hi * n)) * TN + gp];
-        if (c >= r0 && w) mean_acc = fma((double)ph, w[c], mean_acc);
+      const bool ok = c < M;
+      const int cc = ok ? c : 0;
+      const uint4 dq = reinterpret_cast<const uint4*>(midx)[cc];
+      const uint32_t d[4] = {dq.x, dq.y, dq.z, dq.w};
+      float ph = ok ? 1.0f : 0.0f;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int row = (d[j >> 1] >> ((j & 1) * 16)) & 0xffff;
+        ph *= Tf[row * TN + gp];
       }
+      // mean: each column counted in its own column block's stages only
+      const double wsel = w[cc] * ((ok && c >= r0) ? 1.0 : 0.0);
+      mean_acc = fma((double)ph, wsel, mean_acc);
       v[u] = ph;
     }
     uint32_t hh[C::CPT / 2], ll[C::CPT / 2];
@@ -610,7 +635,7 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
       const int q = t + u * kPmThreads;        // 0..1023
       const int term = q >> 9, r = (q >> 1) & 255, half = q & 1;
       const int row = rb * kPmTR + r, c = c0 + half * 8;
-      reg[u] = (row < M && c < P) ? *reinterpret_cast<const uint4*>(lpieces + term * PP + (int64_t)row * P + c)
+      reg[u] = (row < M && c < LP) ? *reinterpret_cast<const uint4*>(lpieces + term * PP + (int64_t)row * LP + c)
                                   : uint4{0u, 0u, 0u, 0u};
     }
   };
@@ -737,9 +762,28 @@ static size_t predict_lds_bytes(int p, int n) {
 // TN = 256 test points per work-group when its FP32 1-D tables fit, else 128.
 static int predict_tn(int p, int n) { return predict_lds_bytes<256>(p, n) <= 160 * 1024 ? 256 : 128; }
 
+typedef void (*PredictKernel)(const double*, int64_t, int, int, const double*, const uint16_t*, const __bf16*,
+                              const double*, int, double*);
+template <int TN>
+static PredictKernel predict_kernel_p(int p) {
+  switch (p) {
+    case 1: return predict_var_mixed_kernel<TN, 1>;
+    case 2: return predict_var_mixed_kernel<TN, 2>;
+    case 3: return predict_var_mixed_kernel<TN, 3>;
+    case 4: return predict_var_mixed_kernel<TN, 4>;
+    case 5: return predict_var_mixed_kernel<TN, 5>;
+    case 6: return predict_var_mixed_kernel<TN, 6>;
+    case 7: return predict_var_mixed_kernel<TN, 7>;
+    default: return predict_var_mixed_kernel<TN, 8>;
+  }
+}
+static PredictKernel predict_kernel_for(int TN, int p) {
+  return TN == 256 ? predict_kernel_p<256>(p) : predict_kernel_p<128>(p);
+}
+
 void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, const double* tab,
-                          const __bf16* linv_pieces, const double* w, double sigma2, double* part, double* mean,
-                          double* var, hipStream_t s, Prof* prof) {
+                          const uint16_t* midx, const __bf16* linv_pieces, const double* w, double sigma2,
+                          double* part, double* mean, double* var, hipStream_t s, Prof* prof) {
   if (Ns <= 0) return;
   const int TN = predict_tn(p, n);
   const int64_t ib = ceil_div(Ns, TN);
@@ -752,12 +796,9 @@ void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, con
   const int rpg = (int)ceil_div(RB, want);
   groups = (int)ceil_div(RB, rpg);
   prof_mark(prof, GP_PH_PREDICT, true, s);
-  if (TN == 256)
-    hipLaunchKernelGGL(predict_var_mixed_kernel<256>, dim3(ib, groups), dim3(kPmThreads), predict_lds_bytes<256>(p, n),
-                       s, xs, Ns, p, n, M, tab, linv_pieces, w, rpg, part);
-  else
-    hipLaunchKernelGGL(predict_var_mixed_kernel<128>, dim3(ib, groups), dim3(kPmThreads), predict_lds_bytes<128>(p, n),
-                       s, xs, Ns, p, n, M, tab, linv_pieces, w, rpg, part);
+  predict_kernel_for(TN, p)<<<dim3(ib, groups), dim3(kPmThreads), TN == 256 ? predict_lds_bytes<256>(p, n)
+                                                                             : predict_lds_bytes<128>(p, n), s>>>(
+      xs, Ns, n, M, tab, midx, linv_pieces, w, rpg, part);
   prof_mark(prof, GP_PH_PREDICT, false, s);
   prof_mark(prof, GP_PH_PREDICT_REDUCE, true, s);
   hipLaunchKernelGGL(predict_mixed_reduce_kernel, dim3(ceil_div(Ns, 256)), dim3(256), 0, s, part, groups, Ns,
@@ -776,9 +817,11 @@ hipError_t configure_kernels() {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)gram_mixed_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)predict_var_mixed_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)predict_var_mixed_kernel<128>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  for (int p = 1; p <= GP_MAX_P; ++p)
+    for (int tn : {128, 256}) {
+      e = hipFuncSetAttribute((const void*)predict_kernel_for(tn, p), hipFuncAttributeMaxDynamicSharedMemorySize, big);
+      if (e != hipSuccess) return e;
+    }
   return e;
 }
 }  // namespace mgp

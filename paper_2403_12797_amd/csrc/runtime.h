@@ -26,6 +26,7 @@ struct gp_model {
   double *tab = nullptr, *lam = nullptr, *reg = nullptr, *A = nullptr, *L = nullptr, *Linv = nullptr,
          *Dinv = nullptr, *w = nullptr, *b = nullptr;
   int* flags = nullptr;  // [0] Cholesky info, [1] non-finite input
+  uint16_t* midx = nullptr;  // [M][8] multi-index table (1-D table rows per column)
   __bf16* linv_pieces = nullptr;
 };
 
