@@ -197,7 +197,7 @@ gp_status gp_fit_batch(gp_ctx* ctx, int32_t count, const gp_params* params, cons
     gp.T = g.T;
     gp.chunk = g.chunk;
     probs.push_back(gp);
-    lds = std::max(lds, gram_mixed_lds_bytes(params[k].p, params[k].n));
+    lds = std::max(lds, gram_mixed_lds_bytes(params[k].p, params[k].n, (int)Ms[k]));
     for (int sp = 0; sp < g.splits_total; ++sp)
       for (int t = 0; t < g.ntiles; ++t)
         for (int h = 0; h < 2; ++h) items.push_back(GramItem{prob_of[k], t, h, sp});

@@ -23,6 +23,10 @@ typedef short i16x8 __attribute__((ext_vector_type(8)));
 //   [3] unused
 constexpr int kDimStride = 4;
 
+// Largest dynamic LDS request of any kernel (160 KB per work-group on gfx950,
+// less 1 KB kept for static __shared__ variables).
+constexpr int kMaxDynLds = 159 * 1024;
+
 // Layout of the per-model constant table (device, float64):
 //   dimc[GP_MAX_P * 4]       per-dimension constants above
 //   rc1[GP_MAX_N], rc2[GP_MAX_N]  normalised Hermite recurrence coefficients

@@ -43,7 +43,7 @@ struct GramPlan {
 GramPlan gram_mixed_plan(int64_t N, int M, int chunk /* <= 0: default */);
 int64_t gram_mixed_part_elems(const GramPlan& g);
 int64_t gram_mixed_table_elems(int64_t N, int p, int n);
-size_t gram_mixed_lds_bytes(int p, int n);
+size_t gram_mixed_lds_bytes(int p, int n, int M);
 void launch_gram_mixed_table(const double* x, int64_t N, int p, int n, const double* tab, float* tab32,
                              hipStream_t s);
 void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const GramPlan& g,

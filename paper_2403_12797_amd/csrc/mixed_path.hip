@@ -123,13 +123,14 @@ int64_t gram_mixed_part_elems(const GramPlan& g) { return (int64_t)g.splits_per_
 // Three zero stages past the end let the kernel prefetch without bounds tests.
 int64_t gram_mixed_table_elems(int64_t N, int p, int n) { return (ceil_div(N, kGmKC) + 3) * p * n * kGmKC; }
 
-// Prefix rows per stage: I-block prefixes then J-half prefixes.
-__host__ __device__ inline int gm_pre_rows_i(int n) { return kGmT / n + 2; }
-__host__ __device__ inline int gm_pre_rows(int n) { return kGmT / n + 2 + kG2H / n + 2; }
+// Prefix rows per stage: I-block prefixes then J-half prefixes (L consecutive
+// columns hold at most L/n + 2 distinct prefixes).
+__host__ __device__ inline int gm_pre_rows_i(int n, int M) { return min(kGmT, M) / n + 2; }
+__host__ __device__ inline int gm_pre_rows(int n, int M) { return gm_pre_rows_i(n, M) + min(kG2H, M) / n + 2; }
 
-static size_t gram_lds_bytes(int p, int n) {
+static size_t gram_lds_bytes(int p, int n, int M) {
   return 2 * (size_t)kGmStageElems * sizeof(__bf16) + 3 * (size_t)p * n * kG2TabPitch * sizeof(float) +
-         2 * (size_t)gm_pre_rows(n) * kG2TabPitch * sizeof(float);
+         2 * (size_t)gm_pre_rows(n, M) * kG2TabPitch * sizeof(float);
 }
 
 // Split NS values into three BF16 terms and store them at [term][slot][s_off..].
@@ -165,7 +166,7 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   const int rows = P * n;                       // 1-D table rows per stage
   const int tbs = rows * kG2TabPitch;           // floats per table buffer
   float* const pr0 = tb0 + 3 * tbs;
-  const int prs = gm_pre_rows(n) * kG2TabPitch; // floats per prefix buffer
+  const int prs = gm_pre_rows(n, M) * kG2TabPitch; // floats per prefix buffer
   const int tchunks = rows * (kGmKC / 4);       // float4 per stage of the table
 
   int I = 0;
@@ -193,7 +194,7 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   const int colJ = cJ0 + (tid >> 2);
   const bool genJ = !diag;
   const bool validJ = genJ && colJ < M;
-  const int preJ = (gm_pre_rows_i(n) + (validJ ? colJ / n - hiJ0 : 0)) * kG2TabPitch + (tid & 3) * 4;
+  const int preJ = (gm_pre_rows_i(n, M) + (validJ ? colJ / n - hiJ0 : 0)) * kG2TabPitch + (tid & 3) * 4;
   const int lastJ = ((P - 1) * n + (validJ ? colJ % n : 0)) * kG2TabPitch + (tid & 3) * 4;
   const int jslot = diag ? h * kG2H : kGmT;  // B operand columns start here in a stage
 
@@ -226,12 +227,12 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   };
   // prefix rows of one stage from its 1-D tables: one (row, 4 samples) per thread
   auto make_pre = [&](const float* Tb, float* dst) {
-    const int npre = gm_pre_rows(n);
+    const int npre = gm_pre_rows(n, M);
     for (int u = tid; u < npre * 4; u += kG2Threads) {
       const int pr = u >> 2, q4 = (u & 3) * 4;
       int hi = -1;
       if (pr < nhiI) hi = hiI0 + pr;
-      else if (pr >= gm_pre_rows_i(n) && pr - gm_pre_rows_i(n) < nhiJ) hi = hiJ0 + pr - gm_pre_rows_i(n);
+      else if (pr >= gm_pre_rows_i(n, M) && pr - gm_pre_rows_i(n, M) < nhiJ) hi = hiJ0 + pr - gm_pre_rows_i(n, M);
       float4 v = float4{1.f, 1.f, 1.f, 1.f};
       if (hi >= 0) {
         int rem = hi;
@@ -419,7 +420,7 @@ __global__ void gram_mixed_reduce_kernel(const float* __restrict__ part, int spl
   A[(int64_t)h * M + g] = s;
 }
 
-size_t gram_mixed_lds_bytes(int p, int n) { return gram_lds_bytes(p, n); }
+size_t gram_mixed_lds_bytes(int p, int n, int M) { return gram_lds_bytes(p, n, M); }
 
 void launch_gram_mixed_table(const double* x, int64_t N, int p, int n, const double* tab, float* tab32,
                              hipStream_t s) {
@@ -437,7 +438,7 @@ void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const Gr
     const int split0 = ps * g.splits_per_pass;
     const int cnt = std::min(g.splits_per_pass, g.splits_total - split0);
     prof_mark(prof, GP_PH_GRAM, true, s);
-    hipLaunchKernelGGL(gram_mixed_kernel, dim3(2 * g.ntiles, cnt), dim3(kG2Threads), gram_lds_bytes(p, n), s, tab32,
+    hipLaunchKernelGGL(gram_mixed_kernel, dim3(2 * g.ntiles, cnt), dim3(kG2Threads), gram_lds_bytes(p, n, M), s, tab32,
                        N, p, n, M, g.T, split0, g.chunk, part);
     prof_mark(prof, GP_PH_GRAM, false, s);
     prof_mark(prof, GP_PH_GRAM_REDUCE, true, s);
@@ -760,7 +761,7 @@ static size_t predict_lds_bytes(int p, int n) {
 }
 
 // TN = 256 test points per work-group when its FP32 1-D tables fit, else 128.
-static int predict_tn(int p, int n) { return predict_lds_bytes<256>(p, n) <= 160 * 1024 ? 256 : 128; }
+static int predict_tn(int p, int n) { return predict_lds_bytes<256>(p, n) <= (size_t)kMaxDynLds ? 256 : 128; }
 
 typedef void (*PredictKernel)(const double*, int64_t, int, int, const double*, const uint16_t*, const __bf16*,
                               const double*, int, double*);
@@ -811,7 +812,8 @@ void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, con
 
 namespace mgp {
 hipError_t configure_kernels() {
-  const int big = 160 * 1024;
+  // dynamic LDS limit: 160 KB per work-group minus room for small static arrays
+  const int big = kMaxDynLds;
   hipError_t e = hipSuccess;
   e = hipFuncSetAttribute((const void*)gram_mixed_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
   if (e != hipSuccess) return e;

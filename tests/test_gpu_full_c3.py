@@ -58,3 +58,28 @@ def test_c3_full_size(setup, precision, tm, tv, tw):
     if tw is not None:
         assert ew <= tw
     m.free()
+
+
+@pytest.mark.parametrize("precision,tm,tv", [(B.PREC_MIXED, 1e-5, 1e-4), (B.PREC_FP64, 1e-10, 1e-10)])
+def test_c2_full_size(precision, tm, tv):
+    """The whole c2 workload (p = 3, n = 8, M = 512, N = N_* = 1e5) against the
+    oracle computed live (a few seconds of CPU)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import mercer_gp as o
+    P = wl.config("c2")
+    print(f"[case] c2 full N={P.N} Ns={P.Ns} precision={precision}", flush=True)
+    f = o.fit(P.x, P.y, P.sigma, P.eps, P.alpha, P.n)
+    om, ov = o.predict(f, P.xs)
+    x, y, xs = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (P.x, P.y, P.xs)]
+    with B.Context(0) as ctx:
+        m = ctx.fit(x, y, p=P.p, n=P.n, sigma=P.sigma, eps=P.eps, alpha=P.alpha, precision=precision)
+        mean = torch.empty(P.Ns, dtype=torch.float64, device="cuda")
+        var = torch.empty_like(mean)
+        ctx.predict(m, xs, mean, var)
+        torch.cuda.synchronize()
+        em, ev = rel(mean.cpu().numpy(), om), rel(var.cpu().numpy(), ov)
+        print(f"[err] c2 full precision={precision}: mean {em:.3e} var {ev:.3e}", flush=True)
+        assert em <= tm and ev <= tv
+        m.free()
