@@ -130,7 +130,8 @@ __host__ __device__ inline int gm_pre_rows(int n, int M) { return gm_pre_rows_i(
 
 static size_t gram_lds_bytes(int p, int n, int M) {
   return 2 * (size_t)kGmStageElems * sizeof(__bf16) + 3 * (size_t)p * n * kG2TabPitch * sizeof(float) +
-         2 * (size_t)gm_pre_rows(n, M) * kG2TabPitch * sizeof(float);
+         2 * (size_t)gm_pre_rows(n, M) * kG2TabPitch * sizeof(float) +
+         (size_t)gm_pre_rows(n, M) * GP_MAX_P * sizeof(uint16_t) + 16;
 }
 
 // Split NS values into three BF16 terms and store them at [term][slot][s_off..].
@@ -167,6 +168,9 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   const int tbs = rows * kG2TabPitch;           // floats per table buffer
   float* const pr0 = tb0 + 3 * tbs;
   const int prs = gm_pre_rows(n, M) * kG2TabPitch; // floats per prefix buffer
+  // per prefix row: the 1-D table rows of its leading digits; entry
+  // GP_MAX_P-1 flags a row with no prefix (value 1 kept out of the sums)
+  uint16_t* const pre_off = reinterpret_cast<uint16_t*>(pr0 + 2 * prs);
   const int tchunks = rows * (kGmKC / 4);       // float4 per stage of the table
 
   int I = 0;
@@ -185,17 +189,20 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   const int nhiI = (min(cI0 + kGmT, M) - 1) / n - hiI0 + 1;   // prefixes used by the I-block
   const int nhiJ = diag ? 0 : (min(cJ0 + kG2H, M) - 1) / n - hiJ0 + 1;
 
-  // generation roles: I-block column tid/2, samples (tid&1)*8..+8;
-  // J-half column tid/4, samples (tid&3)*4..+4 (off-diagonal tiles only)
-  const int colI = cI0 + (tid >> 1);
+  // generation roles (consecutive lanes take consecutive columns, so the
+  // table reads of a wave fall in distinct LDS banks):
+  //   I-block column tid & 255, samples (tid >> 8)*8 .. +8;
+  //   J-half column tid & 127, samples (tid >> 7)*4 .. +4 (off-diagonal tiles only)
+  const int sI = (tid >> 8) * 8, sJ = (tid >> 7) * 4;
+  const int colI = cI0 + (tid & 255);
   const bool validI = colI < M;
-  const int preI = (validI ? colI / n - hiI0 : 0) * kG2TabPitch + (tid & 1) * 8;
-  const int lastI = ((P - 1) * n + (validI ? colI % n : 0)) * kG2TabPitch + (tid & 1) * 8;
-  const int colJ = cJ0 + (tid >> 2);
+  const int preI = (validI ? colI / n - hiI0 : 0) * kG2TabPitch + sI;
+  const int lastI = ((P - 1) * n + (validI ? colI % n : 0)) * kG2TabPitch + sI;
+  const int colJ = cJ0 + (tid & 127);
   const bool genJ = !diag;
   const bool validJ = genJ && colJ < M;
-  const int preJ = (gm_pre_rows_i(n, M) + (validJ ? colJ / n - hiJ0 : 0)) * kG2TabPitch + (tid & 3) * 4;
-  const int lastJ = ((P - 1) * n + (validJ ? colJ % n : 0)) * kG2TabPitch + (tid & 3) * 4;
+  const int preJ = (gm_pre_rows_i(n, M) + (validJ ? colJ / n - hiJ0 : 0)) * kG2TabPitch + sJ;
+  const int lastJ = ((P - 1) * n + (validJ ? colJ % n : 0)) * kG2TabPitch + sJ;
   const int jslot = diag ? h * kG2H : kGmT;  // B operand columns start here in a stage
 
   f32x16 acc[2][2], sum[2][2];
@@ -225,24 +232,22 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
       *reinterpret_cast<float4*>(dst + row * kG2TabPitch + c4 * 4) = treg;
     }
   };
-  // prefix rows of one stage from its 1-D tables: one (row, 4 samples) per thread
+  // prefix rows of one stage from its 1-D tables: one (row, 4 samples) per
+  // thread; the table rows of each prefix (j*n + digit_j) are fixed for the
+  // work-group and were stored in pre_off at the start.
+  const int npre = gm_pre_rows(n, M);
   auto make_pre = [&](const float* Tb, float* dst) {
-    const int npre = gm_pre_rows(n, M);
     for (int u = tid; u < npre * 4; u += kG2Threads) {
       const int pr = u >> 2, q4 = (u & 3) * 4;
-      int hi = -1;
-      if (pr < nhiI) hi = hiI0 + pr;
-      else if (pr >= gm_pre_rows_i(n, M) && pr - gm_pre_rows_i(n, M) < nhiJ) hi = hiJ0 + pr - gm_pre_rows_i(n, M);
+      const uint16_t* po = pre_off + pr * GP_MAX_P;
       float4 v = float4{1.f, 1.f, 1.f, 1.f};
-      if (hi >= 0) {
-        int rem = hi;
-        for (int j = P - 2; j >= 0; --j) {
-          const float4 f = *reinterpret_cast<const float4*>(Tb + (j * n + rem % n) * kG2TabPitch + q4);
+      if (po[GP_MAX_P - 1] == 0) {
+        for (int j = 0; j < P - 1; ++j) {
+          const float4 f = *reinterpret_cast<const float4*>(Tb + po[j] * kG2TabPitch + q4);
           v.x *= f.x;
           v.y *= f.y;
           v.z *= f.z;
           v.w *= f.w;
-          rem /= n;
         }
       }
       *reinterpret_cast<float4*>(dst + pr * kG2TabPitch + q4) = v;
@@ -265,7 +270,7 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = 0.0f;
       }
-      gm_store3<8>(v, D, tid >> 1, (tid & 1) * 8);
+      gm_store3<8>(v, D, tid & 255, sI);
     }
     if (genJ) {
       float v[4];
@@ -276,10 +281,23 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
       v[2] = a.z * b.z;
       v[3] = a.w * b.w;
       if (!validJ) v[0] = v[1] = v[2] = v[3] = 0.0f;
-      gm_store3<4>(v, D, kGmT + (tid >> 2), (tid & 3) * 4);
+      gm_store3<4>(v, D, kGmT + (tid & 127), sJ);
     }
   };
 
+  for (int pr = tid; pr < gm_pre_rows(n, M); pr += kG2Threads) {
+    int hi = -1;
+    if (pr < nhiI) hi = hiI0 + pr;
+    else if (pr >= gm_pre_rows_i(n, M) && pr - gm_pre_rows_i(n, M) < nhiJ) hi = hiJ0 + pr - gm_pre_rows_i(n, M);
+    uint16_t* po = pre_off + pr * GP_MAX_P;
+    int rem = hi < 0 ? 0 : hi;
+    for (int j = P - 2; j >= 0; --j) {
+      po[j] = (uint16_t)(j * n + rem % n);
+      rem /= n;
+    }
+    po[GP_MAX_P - 1] = hi < 0 ? 1 : 0;
+  }
+  // (pre_off is read after the prologue's first barrier)
   // prologue: tables of stages 0..2, prefixes of stages 0..1, Phi of stage 0
   load_tab(st0);
   store_tab(tb0);

@@ -109,8 +109,9 @@ def test_admission_by_budget(torch_cuda):
     torch = torch_cuda
     Ps = problems()[:4]
     keep = []
-    # a budget that fits one request at a time: all still complete, in order
-    with B.Context(0, hbm_budget_bytes=64 << 20) as ctx:
+    # a budget below the sum of the requests' footprints (each fits alone):
+    # requests wait for memory and all still complete
+    with B.Context(0, hbm_budget_bytes=128 << 20) as ctx:
         ids = [submit(ctx, torch, P, B.PREC_MIXED, keep) for P in Ps]
         for rid, mean, var in ids:
             st, _ = ctx.poll(rid, wait_us=-1)
