@@ -272,7 +272,8 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
       }
       gm_store3<8>(v, D, tid & 255, sI);
     }
-    if (genJ) {
+    {
+      // J half (on diagonal tiles these slots are unused and get zeros)
       float v[4];
       const float4 a = *reinterpret_cast<const float4*>(Pr + preJ);
       const float4 b = *reinterpret_cast<const float4*>(Tb + lastJ);
@@ -357,6 +358,15 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
         for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][0], acc[rb][cb]);  // hi*hi
       // stage st+1 (past the chunk end this produces unused values)
       generate(tb0 + ((st + 1) % 3) * tbs, pr0 + ((st + 1) & 1) * prs, stg0 + ((st + 1) & 1) * kGmStageElems);
+      // Interleave the generation's vector work with the MFMAs in program
+      // order: after each MFMA the wave issues a few VALU / LDS instructions
+      // while the matrix pipe works.
+#pragma unroll
+      for (int i = 0; i < 24; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+      }
       make_pre(tb0 + ((st + 2) % 3) * tbs, pr0 + (st & 1) * prs);
       store_tab(tb0 + (st % 3) * tbs);
       __syncthreads();
