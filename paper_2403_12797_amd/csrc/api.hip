@@ -54,16 +54,27 @@ gp_status validate_params(const gp_params* prm, int64_t* M_out) {
   return GP_OK;
 }
 
-// Device bytes a fitted model holds (used by admission control too).
-size_t model_bytes(int64_t M, int precision) {
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Sizes of a model's device regions, in the order model_alloc lays them out.
+static constexpr int kModelRegions = 13;
+static void model_sizes(int64_t M, int precision, size_t* sz) {
   const size_t MM = (size_t)M * M;
-  size_t b = kTabSize * 8 + 4 * M * 8 + 3 * MM * 8 + (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8 +
-             (size_t)M * 16 + 512;
-  if (precision == GP_PREC_MIXED) b += 2 * (size_t)M * linv_pitch((int)M) * 2;
-  return b;
+  const size_t v[kModelRegions] = {kTabSize * 8, (size_t)M * 8, (size_t)M * 8, MM * 8, MM * 8, MM * 8,
+                                   (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8, (size_t)M * 8,
+                                   (size_t)M * 8, 64,
+                                   precision == GP_PREC_MIXED ? 2 * (size_t)M * linv_pitch((int)M) * 2 : 0,
+                                   (size_t)M * 16, (size_t)pdesc_elems((int)M) * 4};
+  for (int r = 0; r < kModelRegions; ++r) sz[r] = v[r];
 }
 
-static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+// Device bytes a fitted model holds (used by admission control too).
+size_t model_bytes(int64_t M, int precision) {
+  size_t sz[kModelRegions], b = 0;
+  model_sizes(M, precision, sz);
+  for (size_t v : sz) b += align_up(v);
+  return b;
+}
 
 FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chunk, bool all_splits) {
   FitLayout L{};
@@ -145,11 +156,8 @@ gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t 
     m->eps[j] = prm->eps[j];
     m->alpha[j] = prm->alpha[j];
   }
-  const size_t MM = (size_t)M * M;
-  const size_t sizes[] = {kTabSize * 8, (size_t)M * 8, (size_t)M * 8, MM * 8, MM * 8, MM * 8,
-                          (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8, (size_t)M * 8, (size_t)M * 8,
-                          64, prm->precision == GP_PREC_MIXED ? 2 * (size_t)M * linv_pitch((int)M) * 2 : 0,
-                          (size_t)M * 16};
+  size_t sizes[kModelRegions];
+  model_sizes(M, prm->precision, sizes);
   size_t total = 0;
   for (size_t s : sizes) total += align_up(s);
   hipError_t e = hipSetDevice(ctx->device);
@@ -179,6 +187,7 @@ gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t 
   m->flags = (int*)take(sizes[9]);
   m->linv_pieces = prm->precision == GP_PREC_MIXED ? (__bf16*)take(sizes[10]) : nullptr;
   m->midx = (uint16_t*)take(sizes[11]);
+  m->pdesc = (uint32_t*)take(sizes[12]);
   *out = m;
   return GP_OK;
 }
@@ -203,6 +212,7 @@ void enqueue_fit_head(gp_model* m, const double* x, const double* y, int64_t N, 
   launch_check_finite(y, N, m->flags + 1, s);
   launch_eig_tables(a, m->tab, m->lam, m->reg, M, s);
   launch_midx(p, n, M, m->midx, s);
+  if (m->precision == GP_PREC_MIXED) launch_pdesc(p, n, M, m->pdesc, s);
   if (m->precision == GP_PREC_MIXED) launch_gram_mixed_table(x, N, p, n, m->tab, (float*)(wb + L.tab32), s);
 }
 
@@ -270,7 +280,8 @@ void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* me
   const double s2 = m->sigma * m->sigma;
   Prof* pr = &m->ctx->prof;
   if (m->precision == GP_PREC_MIXED) {
-    launch_predict_mixed(xs, Ns, p, n, M, m->tab, m->midx, m->linv_pieces, m->w, s2, (double*)ws, mean, var, s, pr);
+    launch_predict_mixed(xs, Ns, p, n, M, m->tab, m->midx, m->pdesc, m->linv_pieces, m->w, s2, (double*)ws, mean,
+                         var, s, pr);
   } else {
     if (mean) {
       prof_mark(pr, GP_PH_PREDICT_MEAN, true, s);

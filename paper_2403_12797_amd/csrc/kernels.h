@@ -89,14 +89,17 @@ int64_t predict_part_elems(int64_t Ns, int M, int* groups_out);
 void launch_predict_var_f64(const double* xs, int64_t Ns, int p, int n, int M, const double* tab,
                             const double* Linv, double sigma2, double* part, double* var,
                             hipStream_t s, Prof* prof = nullptr);
-// a5 mixed: fused mean (FP64 dot with w) and split-BF16 variance.
+// a5 mixed: mean by the FP64 Phi w kernel, variance by split-BF16 MFMA.
 int64_t predict_mixed_part_elems(int64_t Ns, int M, int* groups_out);
 void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, const double* tab,
-                          const uint16_t* midx, const __bf16* linv_pieces, const double* w,
-                          double sigma2, double* part, double* mean, double* var, hipStream_t s,
-                          Prof* prof = nullptr);
+                          const uint16_t* midx, const uint32_t* pdesc, const __bf16* linv_pieces,
+                          const double* w, double sigma2, double* part, double* mean, double* var,
+                          hipStream_t s, Prof* prof = nullptr);
 // Multi-index table: midx[c][j] = j*n + k_j(c), 8 uint16 per column.
 void launch_midx(int p, int n, int M, uint16_t* midx, hipStream_t s);
+// Per-column descriptors of the mixed prediction (pdesc_elems(M) uint32).
+int64_t pdesc_elems(int M);
+void launch_pdesc(int p, int n, int M, uint32_t* pdesc, hipStream_t s);
 
 // Zero fills as kernels (safe inside captured graphs).
 void launch_fill_zero_int(int* p, int count, hipStream_t s);

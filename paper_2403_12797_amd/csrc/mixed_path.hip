@@ -120,8 +120,10 @@ GramPlan gram_mixed_plan(int64_t N, int M, int chunk) {
 
 int64_t gram_mixed_part_elems(const GramPlan& g) { return (int64_t)g.splits_per_pass * g.ntiles * kGmT * kGmT; }
 
-// Three zero stages past the end let the kernel prefetch without bounds tests.
-int64_t gram_mixed_table_elems(int64_t N, int p, int n) { return (ceil_div(N, kGmKC) + 3) * p * n * kGmKC; }
+// Zero stages past the end let the kernel prefetch without bounds tests: a
+// work-group reads at most four stages past its last one.
+constexpr int kGmTabPad = 4;
+int64_t gram_mixed_table_elems(int64_t N, int p, int n) { return (ceil_div(N, kGmKC) + kGmTabPad) * p * n * kGmKC; }
 
 // Prefix rows per stage: I-block prefixes then J-half prefixes (L consecutive
 // columns hold at most L/n + 2 distinct prefixes).
@@ -452,7 +454,7 @@ size_t gram_mixed_lds_bytes(int p, int n, int M) { return gram_lds_bytes(p, n, M
 
 void launch_gram_mixed_table(const double* x, int64_t N, int p, int n, const double* tab, float* tab32,
                              hipStream_t s) {
-  const int64_t nstage = ceil_div(N, kGmKC) + 3;
+  const int64_t nstage = ceil_div(N, kGmKC) + kGmTabPad;
   hipLaunchKernelGGL(phi1d_table_kernel, dim3(ceil_div(nstage * p * kGmKC, 256)), dim3(256), 0, s, x, N, p, n, tab,
                      tab32, nstage);
 }
@@ -539,22 +541,29 @@ void launch_split_linv(const double* Linv, __bf16* pieces, int M, hipStream_t s)
 }
 
 // ================================================================ a5 mixed predict
-// Z = Phi_* L^-T for a tile of TN test points x 256 columns r, over the
-// columns c <= r of L^-1 in stages of 16.  512 threads = 8 waves in a
-// WP (points) x WR (r) grid; each wave owns 64 points x 256/WR columns.
-// Per stage: every thread generates 16*TN/512 columns c of one test point
-// (lane = point, so the column digits are wave-uniform) from the work-group's
-// FP32 1-D tables, splits them in two BF16 terms into LDS; the matching slab
-// of the two L^-1 terms (256 rows x 16 columns) is prefetched into registers
-// one stage ahead.  LDS is double-buffered (one barrier per stage).  After
-// the last stage of a column block the squares of Z are summed per point.
-// The mean sum_c Phi_*[i][c] w[c] (FP64 accumulation) is formed while the
-// columns c of each column block's own diagonal stages are generated, so
-// every c is counted once.
+// Variance part of the prediction: Z = Phi_* L^-T for a tile of TN test
+// points x 256 columns r, over the columns c <= r of L^-1 in stages of 16;
+// var = sigma^2 * sum_r Z^2.  512 threads = 8 waves in a WP (points) x WR (r)
+// grid; each wave owns 64 points x 256/WR columns.
+//
+// Phi_* is formed per stage from the work-group's FP32 1-D tables through
+// the prefix factorisation Phi_*[i][hi*n + k] = PRE[i][hi] * phi_{p-1,k}(x_i):
+// the prefixes of a stage's 16 columns (at most 15/n + 2 of them) are formed
+// one stage ahead into a small LDS table, and every value is then one
+// product of two LDS reads whose rows come from a per-column descriptor
+// (wave-uniform, read through the scalar cache).  Values are split in two
+// BF16 terms into LDS; the matching slab of the two L^-1 terms (256 rows x 16
+// columns) is prefetched into registers one stage ahead.  LDS is
+// double-buffered (one barrier per stage).  After the last stage of a column
+// block the squares of Z are summed per point.  (The mean is formed by the
+// FP64 Phi w kernel.)
 constexpr int kPmTR = 256;
 constexpr int kPmKC = 16;
 constexpr int kPmPitch = kPmKC + 8;     // bf16 per row of a stage buffer (pad against bank conflicts)
 constexpr int kPmThreads = 512;
+
+// distinct prefixes among 16 consecutive columns
+__host__ __device__ inline int pm_pre_rows(int n) { return 15 / n + 2; }
 
 template <int TN>
 struct PmCfg {
@@ -573,22 +582,43 @@ int64_t predict_mixed_part_elems(int64_t Ns, int M, int* groups_out) {
   if (g > RB) g = RB;
   if (g < 1) g = 1;
   if (groups_out) *groups_out = (int)g;
-  return 2 * g * Ns;
+  return g * Ns;
 }
+
+// Per-column descriptor of the prediction: bits 0..15 the 1-D table row of
+// the last factor, (p-1)*n + k; bits 16..31 the prefix row relative to the
+// first prefix of the column's stage of 16.  Columns M .. ceil16(M)-1 point
+// at the zero row p*n.
+__global__ void pdesc_kernel(int p, int n, int M, uint32_t* __restrict__ pdesc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Mp = (int)ceil_div(M, kPmKC) * kPmKC;
+  if (c >= Mp) return;
+  if (c >= M) {
+    pdesc[c] = (uint32_t)(p * n);
+    return;
+  }
+  const int hrel = c / n - (c - c % kPmKC) / n;
+  pdesc[c] = ((uint32_t)hrel << 16) | (uint32_t)((p - 1) * n + c % n);
+}
+
+void launch_pdesc(int p, int n, int M, uint32_t* pdesc, hipStream_t s) {
+  const int Mp = (int)ceil_div(M, kPmKC) * kPmKC;
+  hipLaunchKernelGGL(pdesc_kernel, dim3(ceil_div(Mp, 256)), dim3(256), 0, s, p, n, M, pdesc);
+}
+int64_t pdesc_elems(int M) { return ceil_div(M, kPmKC) * kPmKC; }
 
 template <int TN, int P>
 __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     const double* __restrict__ xs, int64_t Ns, int n, int M, const double* __restrict__ tab,
-    const uint16_t* __restrict__ midx, const __bf16* __restrict__ lpieces, const double* __restrict__ w, int rpg,
-    double* __restrict__ part) {
-  constexpr int p = P;
+    const uint16_t* __restrict__ midx, const uint32_t* __restrict__ pdesc, const __bf16* __restrict__ lpieces,
+    int rpg, double* __restrict__ part) {
   using C = PmCfg<TN>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smraw[];
-  float* const Tf = reinterpret_cast<float*>(smraw);                                  // [p*n][TN]
-  __bf16* const buf0 = reinterpret_cast<__bf16*>(smraw + (size_t)p * n * TN * sizeof(float));
-  // buffer b: Phi_* at buf0 + b*(PHI+LIN), L^-1 slab right after it
-  double* const ssw = reinterpret_cast<double*>(buf0 + 2 * (C::PHI + C::LIN));       // [WR][TN]
-  double* const mred = ssw + C::WR * TN;                                              // [512/TN][TN]
+  const int npr = pm_pre_rows(n);
+  float* const Tf = reinterpret_cast<float*>(smraw);                       // [P*n + 1][TN], row P*n zero
+  float* const pre0 = Tf + (P * n + 1) * TN;                                // [2][npr][TN]
+  __bf16* const buf0 = reinterpret_cast<__bf16*>(pre0 + 2 * npr * TN);      // [2][PHI + LIN]
+  double* const ssw = reinterpret_cast<double*>(buf0 + 2 * (C::PHI + C::LIN));  // [WR][TN]
   const int64_t i0 = (int64_t)blockIdx.x * TN;
   const int RB = (M + kPmTR - 1) / kPmTR;
   const int rb0 = blockIdx.y * rpg, rb1 = min(rb0 + rpg, RB);
@@ -597,50 +627,55 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   const int LP = linv_pitch(M);
   const int64_t PP = (int64_t)M * LP;
 
-  for (int u = t; u < TN * p; u += kPmThreads) {
+  for (int u = t; u < TN * P; u += kPmThreads) {
     const int i = u % TN, j = u / TN;
     float* o = Tf + (j * n) * TN + i;
     if (i0 + i < Ns) {
       const double* dc = tab + kTabDim + j * kDimStride;
-      phi_1d<double, float>(xs[(i0 + i) * p + j], dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, TN);
+      phi_1d<double, float>(xs[(i0 + i) * P + j], dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, TN);
     } else {
       for (int k = 0; k < n; ++k) o[k * TN] = 0.0f;
     }
   }
+  for (int u = t; u < TN; u += kPmThreads) Tf[P * n * TN + u] = 0.0f;
   for (int u = t; u < C::WR * TN; u += kPmThreads) ssw[u] = 0.0;
 
-  // generation role: point gp, columns gq*CPT .. +CPT of each stage (gq is
-  // wave-uniform, so the column indices and table entries are scalar)
+  auto nstages = [&](int rb) { return (int)ceil_div(min(rb * kPmTR + kPmTR, M), kPmKC); };
+  auto advance = [&](int& rb, int& k) {
+    if (++k == nstages(rb)) {
+      ++rb;
+      k = 0;
+    }
+  };
+  // prefixes of stage k (columns 16k .. 16k+15): PRE[r][i] for hi = 16k/n + r
+  auto make_pre = [&](int k, float* dst) {
+    const int hi0 = (k * kPmKC) / n;
+    for (int u = t; u < npr * TN; u += kPmThreads) {
+      const int r = __builtin_amdgcn_readfirstlane(u / TN);
+      const int i = u % TN;
+      int hi = hi0 + r;
+      if (hi * n >= M) hi = 0;   // past the last column: never referenced
+      const uint4 dq = reinterpret_cast<const uint4*>(midx)[hi * n];
+      const uint32_t d[4] = {dq.x, dq.y, dq.z, dq.w};
+      float v = 1.0f;
+#pragma unroll
+      for (int j = 0; j < P - 1; ++j) {
+        const int row = (d[j >> 1] >> ((j & 1) * 16)) & 0xffff;
+        v *= Tf[row * TN + i];
+      }
+      dst[r * TN + i] = v;
+    }
+  };
+  // Phi_* of stage k: point gp, columns gq*CPT .. +CPT (gq wave-uniform)
   const int gp = t % TN;
   const int gq = __builtin_amdgcn_readfirstlane(t / TN);
-  double mean_acc = 0.0;
-
-  // the (column block, stage) sequence of this work-group
-  auto stage_c0 = [](int k) { return k * kPmKC; };
-  auto nstages = [&](int rb) { return (int)ceil_div(min(rb * kPmTR + kPmTR, M), kPmKC); };
-
-  auto gen = [&](int rb, int k, __bf16* phi) {
-    const int c0 = stage_c0(k) + gq * C::CPT;
-    const int r0 = rb * kPmTR;
+  auto gen = [&](int k, const float* pre, __bf16* phi) {
+    const uint32_t* dsc = pdesc + k * kPmKC + gq * C::CPT;
     float v[C::CPT];
 #pragma unroll
     for (int u = 0; u < C::CPT; ++u) {
-      // column c's multi-index table entry (wave-uniform): LDS row j*n + k_j per dimension
-      const int c = c0 + u;
-      const bool ok = c < M;
-      const int cc = ok ? c : 0;
-      const uint4 dq = reinterpret_cast<const uint4*>(midx)[cc];
-      const uint32_t d[4] = {dq.x, dq.y, dq.z, dq.w};
-      float ph = ok ? 1.0f : 0.0f;
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        const int row = (d[j >> 1] >> ((j & 1) * 16)) & 0xffff;
-        ph *= Tf[row * TN + gp];
-      }
-      // mean: each column counted in its own column block's stages only
-      const double wsel = w[cc] * ((ok && c >= r0) ? 1.0 : 0.0);
-      mean_acc = fma((double)ph, wsel, mean_acc);
-      v[u] = ph;
+      const uint32_t d = dsc[u];
+      v[u] = pre[(d >> 16) * TN + gp] * Tf[(d & 0xffff) * TN + gp];
     }
     uint32_t hh[C::CPT / 2], ll[C::CPT / 2];
 #pragma unroll
@@ -658,7 +693,7 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   // L^-1 slab (rows r0..r0+255, columns c0..c0+15, both terms): 1024 uint4,
   // two per thread.  Rows past M read as zero; padding columns are zero.
   auto lin_load = [&](int rb, int k, uint4* reg) {
-    const int c0 = stage_c0(k);
+    const int c0 = k * kPmKC;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int q = t + u * kPmThreads;        // 0..1023
@@ -680,12 +715,20 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   __syncthreads();  // tables ready
   if (rb0 < rb1) {
     uint4 lreg[2];
-    // prologue: stage (rb0, 0) into buffer 0
-    gen(rb0, 0, buf0);
+    // prologue: prefixes of the first stage, then its Phi_* and L^-1 slab
+    // into buffer 0 and the second stage's prefixes into prefix buffer 1
+    make_pre(0, pre0);
+    __syncthreads();
+    gen(0, pre0, buf0);
     lin_load(rb0, 0, lreg);
     lin_store(buf0 + C::PHI, lreg);
+    {
+      int nrb = rb0, nk = 0;
+      advance(nrb, nk);
+      if (nrb < rb1) make_pre(nk, pre0 + npr * TN);
+    }
     __syncthreads();
-    int b = 0;
+    int b = 0, pb = 1;   // stage buffer of the current stage; prefix buffer of the next
     for (int rb = rb0; rb < rb1; ++rb) {
       const int ns = nstages(rb);
       f32x16 acc[2][C::CB];
@@ -696,13 +739,11 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
 #pragma unroll
           for (int r = 0; r < 16; ++r) acc[a][cb][r] = 0.0f;
       for (int k = 0; k < ns; ++k) {
-        // next stage in the sequence
-        int nrb = rb, nk = k + 1;
-        if (nk == ns) {
-          nrb = rb + 1;
-          nk = 0;
-        }
-        const bool has_next = nrb < rb1;
+        int nrb = rb, nk = k;
+        advance(nrb, nk);
+        int n2rb = nrb, n2k = nk;
+        advance(n2rb, n2k);
+        const bool has_next = nrb < rb1, has_next2 = n2rb < rb1;
         if (has_next) lin_load(nrb, nk, lreg);
         const __bf16* PHs = buf0 + b * (C::PHI + C::LIN);
         const __bf16* LNs = PHs + C::PHI;
@@ -733,11 +774,13 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
           for (int cb = 0; cb < C::CB; ++cb) acc[a][cb] = mfma_bf16(aop[a][0], bop[cb][0], acc[a][cb]);
         if (has_next) {
           __bf16* nb = buf0 + (b ^ 1) * (C::PHI + C::LIN);
-          gen(nrb, nk, nb);
+          gen(nk, pre0 + pb * npr * TN, nb);
           lin_store(nb + C::PHI, lreg);
         }
+        if (has_next2) make_pre(n2k, pre0 + (pb ^ 1) * npr * TN);
         __syncthreads();
         b ^= 1;
+        pb ^= 1;
       }
       // squares of this column block, summed over the wave's columns
 #pragma unroll
@@ -757,42 +800,35 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
         }
     }
   }
-  mred[gq * TN + gp] = mean_acc;
   __syncthreads();
   if (t < TN && i0 + t < Ns) {
-    double v = 0.0, mu = 0.0;
+    double v = 0.0;
     for (int q = 0; q < C::WR; ++q) v += ssw[q * TN + t];
-    for (int q = 0; q < kPmThreads / TN; ++q) mu += mred[q * TN + t];
-    part[(int64_t)blockIdx.y * 2 * Ns + i0 + t] = v;
-    part[(int64_t)blockIdx.y * 2 * Ns + Ns + i0 + t] = mu;
+    part[(int64_t)blockIdx.y * Ns + i0 + t] = v;
   }
 }
 
 __global__ void predict_mixed_reduce_kernel(const double* __restrict__ part, int groups, int64_t Ns, double sigma2,
-                                            double* __restrict__ mean, double* __restrict__ var) {
+                                            double* __restrict__ var) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Ns) return;
-  double v = 0.0, mu = 0.0;
-  for (int g = 0; g < groups; ++g) {
-    v += part[(int64_t)g * 2 * Ns + i];
-    mu += part[(int64_t)g * 2 * Ns + Ns + i];
-  }
-  if (var) var[i] = sigma2 * v;
-  if (mean) mean[i] = mu;
+  double v = 0.0;
+  for (int g = 0; g < groups; ++g) v += part[(int64_t)g * Ns + i];
+  var[i] = sigma2 * v;
 }
 
 template <int TN>
 static size_t predict_lds_bytes(int p, int n) {
   using C = PmCfg<TN>;
-  return (size_t)p * n * TN * sizeof(float) + 2 * (C::PHI + C::LIN) * sizeof(__bf16) +
-         (size_t)(C::WR + kPmThreads / TN) * TN * sizeof(double);
+  return ((size_t)(p * n + 1) + 2 * (size_t)pm_pre_rows(n)) * TN * sizeof(float) +
+         2 * (C::PHI + C::LIN) * sizeof(__bf16) + (size_t)C::WR * TN * sizeof(double);
 }
 
-// TN = 256 test points per work-group when its FP32 1-D tables fit, else 128.
+// TN = 256 test points per work-group when its tables fit, else 128.
 static int predict_tn(int p, int n) { return predict_lds_bytes<256>(p, n) <= (size_t)kMaxDynLds ? 256 : 128; }
 
-typedef void (*PredictKernel)(const double*, int64_t, int, int, const double*, const uint16_t*, const __bf16*,
-                              const double*, int, double*);
+typedef void (*PredictKernel)(const double*, int64_t, int, int, const double*, const uint16_t*, const uint32_t*,
+                              const __bf16*, int, double*);
 template <int TN>
 static PredictKernel predict_kernel_p(int p) {
   switch (p) {
@@ -811,9 +847,15 @@ static PredictKernel predict_kernel_for(int TN, int p) {
 }
 
 void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, const double* tab,
-                          const uint16_t* midx, const __bf16* linv_pieces, const double* w, double sigma2,
-                          double* part, double* mean, double* var, hipStream_t s, Prof* prof) {
+                          const uint16_t* midx, const uint32_t* pdesc, const __bf16* linv_pieces, const double* w,
+                          double sigma2, double* part, double* mean, double* var, hipStream_t s, Prof* prof) {
   if (Ns <= 0) return;
+  if (mean) {
+    prof_mark(prof, GP_PH_PREDICT_MEAN, true, s);
+    launch_phi_matvec(xs, Ns, p, n, M, tab, w, nullptr, mean, s);
+    prof_mark(prof, GP_PH_PREDICT_MEAN, false, s);
+  }
+  if (!var) return;
   const int TN = predict_tn(p, n);
   const int64_t ib = ceil_div(Ns, TN);
   const int RB = (int)ceil_div(M, kPmTR);
@@ -827,11 +869,11 @@ void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, con
   prof_mark(prof, GP_PH_PREDICT, true, s);
   predict_kernel_for(TN, p)<<<dim3(ib, groups), dim3(kPmThreads), TN == 256 ? predict_lds_bytes<256>(p, n)
                                                                              : predict_lds_bytes<128>(p, n), s>>>(
-      xs, Ns, n, M, tab, midx, linv_pieces, w, rpg, part);
+      xs, Ns, n, M, tab, midx, pdesc, linv_pieces, rpg, part);
   prof_mark(prof, GP_PH_PREDICT, false, s);
   prof_mark(prof, GP_PH_PREDICT_REDUCE, true, s);
   hipLaunchKernelGGL(predict_mixed_reduce_kernel, dim3(ceil_div(Ns, 256)), dim3(256), 0, s, part, groups, Ns,
-                     sigma2, mean, var);
+                     sigma2, var);
   prof_mark(prof, GP_PH_PREDICT_REDUCE, false, s);
 }
 

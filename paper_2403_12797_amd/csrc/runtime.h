@@ -27,6 +27,7 @@ struct gp_model {
          *Dinv = nullptr, *w = nullptr, *b = nullptr;
   int* flags = nullptr;  // [0] Cholesky info, [1] non-finite input
   uint16_t* midx = nullptr;  // [M][8] multi-index table (1-D table rows per column)
+  uint32_t* pdesc = nullptr; // [ceil16(M)] prediction column descriptors
   __bf16* linv_pieces = nullptr;
 };
 
