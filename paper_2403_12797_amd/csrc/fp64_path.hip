@@ -189,86 +189,119 @@ constexpr int kNbLd = kNb + 1;
 
 __global__ void __launch_bounds__(256) potrf_diag_kernel(double* __restrict__ A, int M, int k0,
                                                          double* __restrict__ Dinv, int* __restrict__ info) {
-  // Factor the diagonal block B = L L^T and form X = L^-1 in the same sweep:
-  // step j takes the pivot, scales column j of L and row j of X
-  // (X[j][:] = R[j][:] / L[j][j]), then updates the trailing block of B and
-  // the rows R[i][:] = e_i - sum_{q<j} L[i][q] X[q][:] of the rows below.
-  // Thread t owns row t/4 and every fourth column starting at t%4.
-  __shared__ double a[kNb * kNbLd];
-  __shared__ double x[kNb * kNbLd];
-  __shared__ int bad;
+  // Factor the diagonal block B = L L^T and form X = L^-1 together, by row
+  // elimination on W = [B | I] (64 x 128): step j takes the pivot
+  // sqrt(W[j][j]), then every row i > j subtracts l_ij / piv times the
+  // pivot row (l_ij = W[i][j] / piv = L[i][j]) and row j is divided by the
+  // pivot.  The trailing part of B stays symmetric, so the pivot row also
+  // supplies column j, and only the pivot row is exchanged (through LDS,
+  // double-buffered).  Afterwards the right half of W is X.  Thread t owns
+  // row i = t/4 and the 32 columns t%4 + 4q of W in registers.  Rows and
+  // columns past the matrix are the identity.
+  __shared__ double prow[2][2 * kNb];
+  __shared__ double Ls[kNb * kNbLd];
   if (*info) return;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, wv = t >> 6;
   const int nb = min(kNb, M - k0);
-  const int ri = t >> 2, c0 = t & 3;
-  for (int c = c0; c < kNb; c += 4) {
-    a[ri * kNbLd + c] = (ri < nb && c < nb && c <= ri) ? A[(int64_t)(k0 + ri) * M + k0 + c] : 0.0;
-    x[ri * kNbLd + c] = (ri == c) ? 1.0 : 0.0;
+  const int i = t >> 2, c0 = t & 3;
+  double w[32];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = c0 + 4 * q;
+    const int r = i > c ? i : c, cc = i > c ? c : i;   // lower triangle of the block
+    w[q] = (i < nb && c < nb) ? A[(int64_t)(k0 + r) * M + k0 + cc] : (i == c ? 1.0 : 0.0);
+    w[16 + q] = (i == c) ? 1.0 : 0.0;
   }
-  if (t == 0) bad = 0;
+  if (i == 0) {
+#pragma unroll
+    for (int q = 0; q < 32; ++q) prow[0][c0 + 4 * q] = w[q];
+  }
+  for (int j = 0; j < kNb; ++j) {
+    __syncthreads();
+    const int bs = j & 1;
+    const double d = prow[bs][j];
+    if (!(d > 0.0) || !isfinite(d)) {   // same value in every thread
+      if (t == 0) *info = k0 + j + 1;
+      return;
+    }
+    const double piv = sqrt(d), rp = 1.0 / piv;
+    if (wv * 16 + 15 >= j) {            // waves whose rows are all above j are done
+      if (i == j) {
+#pragma unroll
+        for (int q = 0; q < 32; ++q) w[q] *= rp;
+      } else {
+        const double l = (i > j) ? prow[bs][i] * rp : 0.0;
+        const double lr = l * rp;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) w[q] = fma(-lr, prow[bs][c0 + 4 * q], w[q]);
+        if (c0 == 0 && i > j) Ls[i * kNbLd + j] = l;
+      }
+      if (i == j && c0 == 0) Ls[j * kNbLd + j] = piv;
+      if (i == j + 1) {
+#pragma unroll
+        for (int q = 0; q < 32; ++q) prow[bs ^ 1][c0 + 4 * q] = w[q];
+      }
+    }
+  }
   __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (t == 0) {
-      const double d = a[j * kNbLd + j];
-      if (!(d > 0.0) || !isfinite(d))
-        bad = k0 + j + 1;
-      else
-        a[j * kNbLd + j] = sqrt(d);
-    }
-    __syncthreads();
-    if (bad) break;
-    const double piv = a[j * kNbLd + j];
-    const double rp = 1.0 / piv;
-    if (ri > j && ri < nb && c0 == 0) a[ri * kNbLd + j] *= rp;
-    if (ri == j)
-      for (int c = c0; c <= j; c += 4) x[j * kNbLd + c] *= rp;
-    __syncthreads();
-    if (ri > j && ri < nb) {
-      const double lij = a[ri * kNbLd + j];
-      for (int c = j + 1 + c0; c <= ri; c += 4) a[ri * kNbLd + c] -= lij * a[c * kNbLd + j];
-      for (int c = c0; c <= j; c += 4) x[ri * kNbLd + c] -= lij * x[j * kNbLd + c];
-    }
-    __syncthreads();
-  }
-  if (bad) {
-    if (t == 0) *info = bad;
-    return;
-  }
   double* D = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
-  for (int c = c0; c < kNb; c += 4) {
-    D[ri * kNb + c] = (ri < nb && c < nb && c <= ri) ? x[ri * kNbLd + c] : 0.0;
-    if (ri < nb && c < nb) A[(int64_t)(k0 + ri) * M + k0 + c] = (c <= ri) ? a[ri * kNbLd + c] : 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = c0 + 4 * q;
+    D[i * kNb + c] = (i < nb && c < nb && c <= i) ? w[16 + q] : 0.0;
+    if (i < nb && c < nb) A[(int64_t)(k0 + i) * M + k0 + c] = (c <= i) ? Ls[i * kNbLd + c] : 0.0;
   }
 }
 
-// Panel rows below the diagonal block: L_rk = A_rk L_kk^-T.
+// Panel below the diagonal block: L21 = B21 L11^-T = B21 X^T as one 64x64x64
+// FP64-MFMA product per 64-row block (X lower, zero above the diagonal).
 __global__ void __launch_bounds__(256) trsm_panel_kernel(double* __restrict__ A, int M, int k0,
                                                          const double* __restrict__ Dinv,
                                                          const int* __restrict__ info) {
-  __shared__ double X[kNb * kNbLd];
-  __shared__ double D[kNb * kNbLd];
+  __shared__ double Bs[kNb * kNbLd];        // B21 rows [m][k]
+  __shared__ double Xt[kNb * (kNb + 2)];    // X^T [k][n] = X[n][k]
   if (*info) return;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int wr = wv >> 1, wc = wv & 1;
   const int R0 = k0 + kNb + blockIdx.x * kNb;
   const double* Dk = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
-  for (int idx = t; idx < kNb * kNb; idx += 256) {
-    const int i = idx / kNb, c = idx % kNb;
-    X[i * kNbLd + c] = (R0 + i < M) ? A[(int64_t)(R0 + i) * M + k0 + c] : 0.0;
-    D[i * kNbLd + c] = Dk[idx];
+  for (int u = t; u < kNb * kNb; u += 256) {
+    const int r = u >> 6, c = u & 63;
+    Bs[r * kNbLd + c] = (R0 + r < M) ? A[(int64_t)(R0 + r) * M + k0 + c] : 0.0;
+    Xt[c * (kNb + 2) + r] = Dk[u];
   }
   __syncthreads();
-  const int i = t >> 2, cbase = (t & 3) * 16;
-  if (R0 + i >= M) return;
-  for (int cc = 0; cc < 16; ++cc) {
-    const int c = cbase + cc;
-    double s = 0.0;
-    for (int q = 0; q <= c; ++q) s = fma(X[i * kNbLd + q], D[c * kNbLd + q], s);
-    A[(int64_t)(R0 + i) * M + k0 + c] = s;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < kNb / 4; ++kk) {
+    const int k = kk * 4 + (lane >> 4);
+    double av[2], bv[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      av[q] = Bs[(wr * 32 + q * 16 + (lane & 15)) * kNbLd + k];
+      bv[q] = Xt[k * (kNb + 2) + wc * 32 + q * 16 + (lane & 15)];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
   }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = R0 + wr * 32 + a * 16 + 4 * q + (lane >> 4);
+        const int col = k0 + wc * 32 + b * 16 + (lane & 15);
+        if (row < M) A[(int64_t)row * M + col] = acc[a][b][q];
+      }
 }
 
-// Trailing update of lower tiles (R >= C) of the region past the panel:
-// A_RC -= P_R P_C^T, P = A[:, k0:k0+64].
 __global__ void __launch_bounds__(256) syrk_trailing_kernel(double* __restrict__ A, int M, int k0,
                                                             const int* __restrict__ info) {
   __shared__ double PR[kNb * kNbLd];

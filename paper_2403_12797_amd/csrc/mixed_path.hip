@@ -255,18 +255,30 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
       *reinterpret_cast<float4*>(dst + pr * kG2TabPitch + q4) = v;
     }
   };
-  auto generate = [&](const float* Tb, const float* Pr, __bf16* D) {
+  // generation inputs of one stage (prefix and last-factor values) into
+  // registers, then products, split and store
+  struct GenIn {
+    float4 pa[2], la[2], pj, lj;
+  };
+  auto gen_read = [&](const float* Tb, const float* Pr, GenIn& g) {
+    const float4* pa = reinterpret_cast<const float4*>(Pr + preI);
+    const float4* la = reinterpret_cast<const float4*>(Tb + lastI);
+    g.pa[0] = pa[0];
+    g.pa[1] = pa[1];
+    g.la[0] = la[0];
+    g.la[1] = la[1];
+    g.pj = *reinterpret_cast<const float4*>(Pr + preJ);
+    g.lj = *reinterpret_cast<const float4*>(Tb + lastJ);
+  };
+  auto gen_store = [&](const GenIn& g, __bf16* D) {
     {
       float v[8];
-      const float4* pa = reinterpret_cast<const float4*>(Pr + preI);
-      const float4* la = reinterpret_cast<const float4*>(Tb + lastI);
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const float4 a = pa[q], b = la[q];
-        v[4 * q] = a.x * b.x;
-        v[4 * q + 1] = a.y * b.y;
-        v[4 * q + 2] = a.z * b.z;
-        v[4 * q + 3] = a.w * b.w;
+        v[4 * q] = g.pa[q].x * g.la[q].x;
+        v[4 * q + 1] = g.pa[q].y * g.la[q].y;
+        v[4 * q + 2] = g.pa[q].z * g.la[q].z;
+        v[4 * q + 3] = g.pa[q].w * g.la[q].w;
       }
       if (!validI) {
 #pragma unroll
@@ -277,15 +289,18 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
     {
       // J half (on diagonal tiles these slots are unused and get zeros)
       float v[4];
-      const float4 a = *reinterpret_cast<const float4*>(Pr + preJ);
-      const float4 b = *reinterpret_cast<const float4*>(Tb + lastJ);
-      v[0] = a.x * b.x;
-      v[1] = a.y * b.y;
-      v[2] = a.z * b.z;
-      v[3] = a.w * b.w;
+      v[0] = g.pj.x * g.lj.x;
+      v[1] = g.pj.y * g.lj.y;
+      v[2] = g.pj.z * g.lj.z;
+      v[3] = g.pj.w * g.lj.w;
       if (!validJ) v[0] = v[1] = v[2] = v[3] = 0.0f;
       gm_store3<4>(v, D, kGmT + (tid & 127), sJ);
     }
+  };
+  auto generate = [&](const float* Tb, const float* Pr, __bf16* D) {
+    GenIn g;
+    gen_read(Tb, Pr, g);
+    gen_store(g, D);
   };
 
   for (int pr = tid; pr < gm_pre_rows(n, M); pr += kG2Threads) {
@@ -319,6 +334,9 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
     const int gend = min(g0 + kG2Flush, nst);
     for (int st = g0; st < gend; ++st) {
       load_tab(st0 + st + 3);
+      // inputs of stage st+1 (past the chunk end they produce unused values)
+      GenIn gin;
+      gen_read(tb0 + ((st + 1) % 3) * tbs, pr0 + ((st + 1) & 1) * prs, gin);
       const __bf16* S = stg0 + (st & 1) * kGmStageElems;
       bf16x8 aop[2][3], bop[2][3];
 #pragma unroll
@@ -358,17 +376,7 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
       for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][0], acc[rb][cb]);  // hi*hi
-      // stage st+1 (past the chunk end this produces unused values)
-      generate(tb0 + ((st + 1) % 3) * tbs, pr0 + ((st + 1) & 1) * prs, stg0 + ((st + 1) & 1) * kGmStageElems);
-      // Interleave the generation's vector work with the MFMAs in program
-      // order: after each MFMA the wave issues a few VALU / LDS instructions
-      // while the matrix pipe works.
-#pragma unroll
-      for (int i = 0; i < 24; ++i) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
-      }
+      gen_store(gin, stg0 + ((st + 1) & 1) * kGmStageElems);
       make_pre(tb0 + ((st + 2) % 3) * tbs, pr0 + (st & 1) * prs);
       store_tab(tb0 + (st % 3) * tbs);
       __syncthreads();
@@ -669,14 +677,19 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   // Phi_* of stage k: point gp, columns gq*CPT .. +CPT (gq wave-uniform)
   const int gp = t % TN;
   const int gq = __builtin_amdgcn_readfirstlane(t / TN);
-  auto gen = [&](int k, const float* pre, __bf16* phi) {
+  auto gen_read = [&](int k, const float* pre, float* ga, float* gb) {
     const uint32_t* dsc = pdesc + k * kPmKC + gq * C::CPT;
-    float v[C::CPT];
 #pragma unroll
     for (int u = 0; u < C::CPT; ++u) {
       const uint32_t d = dsc[u];
-      v[u] = pre[(d >> 16) * TN + gp] * Tf[(d & 0xffff) * TN + gp];
+      ga[u] = pre[(d >> 16) * TN + gp];
+      gb[u] = Tf[(d & 0xffff) * TN + gp];
     }
+  };
+  auto gen_store = [&](const float* ga, const float* gb, __bf16* phi) {
+    float v[C::CPT];
+#pragma unroll
+    for (int u = 0; u < C::CPT; ++u) v[u] = ga[u] * gb[u];
     uint32_t hh[C::CPT / 2], ll[C::CPT / 2];
 #pragma unroll
     for (int q = 0; q < C::CPT / 2; ++q) split2(v[2 * q], v[2 * q + 1], hh[q], ll[q]);
@@ -689,6 +702,11 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
       *reinterpret_cast<uint2*>(dh) = uint2{hh[0], hh[1]};
       *reinterpret_cast<uint2*>(dl) = uint2{ll[0], ll[1]};
     }
+  };
+  auto gen = [&](int k, const float* pre, __bf16* phi) {
+    float ga[C::CPT], gb[C::CPT];
+    gen_read(k, pre, ga, gb);
+    gen_store(ga, gb, phi);
   };
   // L^-1 slab (rows r0..r0+255, columns c0..c0+15, both terms): 1024 uint4,
   // two per thread.  Rows past M read as zero; padding columns are zero.
@@ -744,7 +762,11 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
         int n2rb = nrb, n2k = nk;
         advance(n2rb, n2k);
         const bool has_next = nrb < rb1, has_next2 = n2rb < rb1;
-        if (has_next) lin_load(nrb, nk, lreg);
+        // (past the last stage the next-stage work reads valid memory and
+        // writes a buffer that is not read again)
+        lin_load(nrb, nk, lreg);
+        float ga[C::CPT], gb[C::CPT];
+        gen_read(nk, pre0 + pb * npr * TN, ga, gb);
         const __bf16* PHs = buf0 + b * (C::PHI + C::LIN);
         const __bf16* LNs = PHs + C::PHI;
         bf16x8 aop[2][2], bop[C::CB][2];
@@ -772,9 +794,9 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
         for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int cb = 0; cb < C::CB; ++cb) acc[a][cb] = mfma_bf16(aop[a][0], bop[cb][0], acc[a][cb]);
-        if (has_next) {
+        {
           __bf16* nb = buf0 + (b ^ 1) * (C::PHI + C::LIN);
-          gen(nk, pre0 + pb * npr * TN, nb);
+          gen_store(ga, gb, nb);
           lin_store(nb + C::PHI, lreg);
         }
         if (has_next2) make_pre(n2k, pre0 + (pb ^ 1) * npr * TN);
