@@ -12,6 +12,7 @@ gp_fit + gp_predict(mean, var) with inputs resident in HBM; value =
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -198,6 +199,32 @@ def cpu_baseline(P_full, target_s):
                       f"includes the fixed M^3 factorisation, so it understates the oracle's large-N rate"}
 
 
+def gram_source_fingerprint():
+    """sha256 of the Gram kernel section of mixed_path.hip (constants, table
+    kernel, plan, work item and kernels; not the launchers)."""
+    src = open(os.path.join(ROOT, "paper_2403_12797_amd", "csrc", "mixed_path.hip")).read()
+    a = src.index("// ================================================================ a3 mixed Gram")
+    b = src.index("__global__ void reset_counter_kernel")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def gram_traffic(P, launches_per_step):
+    """HBM bytes per Gram launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record, scaled by the copy-kernel calibration; None when the
+    record is for another workload or the kernel source has changed since."""
+    path = os.path.join(ROOT, "profiles", "gram_mixed_kernel_c3_hbm.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None, "no counter record"
+    if rec.get("N") != P.N or rec.get("M") != P.M or rec.get("workload") != P.name:
+        return None, "counter record is for another workload"
+    if rec.get("source_fingerprint") != gram_source_fingerprint():
+        return None, "kernel changed since the counters were taken"
+    kib = sum(rec["fetch_kib_per_launch"]) * rec["fetch_factor"] + sum(rec["write_kib_per_launch"]) * rec["write_factor"]
+    return kib * 1024.0 / len(rec["fetch_kib_per_launch"]), "bytes per launch, " + os.path.basename(path)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -246,6 +273,7 @@ def main():
     issued = 6.0 * achieved * (2.0 * 65536 * (((P.M + 255) // 256) * ((P.M + 255) // 256 + 1) // 2)) / \
         (P.M * (P.M + 1))
     pv_ms = prof_mx["predict"][0] / steps
+    traffic, traffic_note = gram_traffic(P, launches_per_step)
     out = {
         "metric": METRIC, "value": (P.N + P.Ns) / dt_mx, "unit": "points/s", "n_gpus": 1, "steps": steps,
         "warmup": a.warmup, "ms_per_step": dt_mx * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -257,7 +285,7 @@ def main():
                    "precision": "mixed"},
         "roofline": {"kernel": "gram_mixed_kernel", "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_BF16,
-                     "traffic": None, "launches_per_step": launches_per_step,
+                     "traffic": traffic, "traffic_note": traffic_note, "launches_per_step": launches_per_step,
                      "avg_launch_ms": avg_launch_ms, "algorithmic_flops_per_step": flops_per_step,
                      "mfma_issue_frac": issued / PEAK_BF16,
                      "predict_kernel_frac": (P.Ns * P.M * (P.M + 1)) / (pv_ms * 1e-3) / PEAK_BF16},

@@ -29,14 +29,22 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
   bf16x2_t v = {(__bf16)a, (__bf16)b};
   return __builtin_bit_cast(uint32_t, v);
 }
+// The same with the packed word kept opaque to the compiler (an empty asm):
+// otherwise it re-derives each unpacked half with a second conversion of
+// one value, which costs a VALU instruction per half.
+__device__ __forceinline__ uint32_t pack_bf16x2_opaque(float a, float b) {
+  uint32_t w = pack_bf16x2(a, b);
+  asm volatile("" : "+v"(w));
+  return w;
+}
 __device__ __forceinline__ float bf16lo_f(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16hi_f(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
 // Three-term split of a pair of FP32 values; returns packed (hi, mid, lo).
 __device__ __forceinline__ void split3(float a, float b, uint32_t& h, uint32_t& m, uint32_t& l) {
-  h = pack_bf16x2(a, b);
+  h = pack_bf16x2_opaque(a, b);
   const float ra = a - bf16lo_f(h), rb = b - bf16hi_f(h);
-  m = pack_bf16x2(ra, rb);
+  m = pack_bf16x2_opaque(ra, rb);
   const float sa = ra - bf16lo_f(m), sb = rb - bf16hi_f(m);
   l = pack_bf16x2(sa, sb);
 }
@@ -224,14 +232,16 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   const int64_t st0 = r0 / kGmKC;
 
   // 1-D tables of one stage: at most 128 rows x 16 floats = 512 float4, one per thread
-  float4 treg;
-  auto load_tab = [&](int64_t gst) {
-    if (tid < tchunks) treg = reinterpret_cast<const float4*>(tab32 + gst * rows * kGmKC)[tid];
+  // (requested two stages before they are stored, alternating between two
+  // registers, so the global latency is hidden behind two stages of work)
+  float4 treg0, treg1;
+  auto load_tab = [&](int64_t gst, float4& r) {
+    if (tid < tchunks) r = reinterpret_cast<const float4*>(tab32 + gst * rows * kGmKC)[tid];
   };
-  auto store_tab = [&](float* dst) {
+  auto store_tab = [&](float* dst, const float4& r) {
     if (tid < tchunks) {
       const int row = tid / (kGmKC / 4), c4 = tid % (kGmKC / 4);
-      *reinterpret_cast<float4*>(dst + row * kG2TabPitch + c4 * 4) = treg;
+      *reinterpret_cast<float4*>(dst + row * kG2TabPitch + c4 * 4) = r;
     }
   };
   // prefix rows of one stage from its 1-D tables: one (row, 4 samples) per
@@ -317,12 +327,13 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   }
   // (pre_off is read after the prologue's first barrier)
   // prologue: tables of stages 0..2, prefixes of stages 0..1, Phi of stage 0
-  load_tab(st0);
-  store_tab(tb0);
-  load_tab(st0 + 1);
-  store_tab(tb0 + tbs);
-  load_tab(st0 + 2);
-  store_tab(tb0 + 2 * tbs);
+  load_tab(st0, treg0);
+  store_tab(tb0, treg0);
+  load_tab(st0 + 1, treg0);
+  store_tab(tb0 + tbs, treg0);
+  load_tab(st0 + 2, treg0);
+  store_tab(tb0 + 2 * tbs, treg0);
+  load_tab(st0 + 3, treg1);
   __syncthreads();
   make_pre(tb0, pr0);
   make_pre(tb0 + tbs, pr0 + prs);
@@ -330,56 +341,64 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   generate(tb0, pr0, stg0);
   __syncthreads();
 
+  // one stage: MFMAs on stage st, generation of st+1, prefixes of st+2,
+  // tables of st+3 stored (from Rstore, requested one stage earlier) and
+  // tables of st+4 requested into Rload.  Stages alternate the registers.
+  auto stage = [&](int st, float4& Rload, const float4& Rstore) {
+    load_tab(st0 + st + 4, Rload);
+    // inputs of stage st+1 (past the chunk end they produce unused values)
+    GenIn gin;
+    gen_read(tb0 + ((st + 1) % 3) * tbs, pr0 + ((st + 1) & 1) * prs, gin);
+    const __bf16* S = stg0 + (st & 1) * kGmStageElems;
+    bf16x8 aop[2][3], bop[2][3];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        bop[cb][q] = *reinterpret_cast<const bf16x8*>(
+            S + (q * kG2Slots + jslot + wc * 64 + cb * 32 + (lane & 31)) * kG2SlotPitch + (lane >> 5) * 8);
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        aop[rb][q] = *reinterpret_cast<const bf16x8*>(
+            S + (q * kG2Slots + wr * 64 + rb * 32 + (lane & 31)) * kG2SlotPitch + (lane >> 5) * 8);
+    // six products, interleaved over the four accumulators
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][1], bop[cb][1], acc[rb][cb]);  // mid*mid
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][2], bop[cb][0], acc[rb][cb]);  // lo*hi
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][2], acc[rb][cb]);  // hi*lo
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][1], bop[cb][0], acc[rb][cb]);  // mid*hi
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][1], acc[rb][cb]);  // hi*mid
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][0], acc[rb][cb]);  // hi*hi
+    gen_store(gin, stg0 + ((st + 1) & 1) * kGmStageElems);
+    make_pre(tb0 + ((st + 2) % 3) * tbs, pr0 + (st & 1) * prs);
+    store_tab(tb0 + (st % 3) * tbs, Rstore);
+    __syncthreads();
+  };
+
   for (int g0 = 0; g0 < nst; g0 += kG2Flush) {
     const int gend = min(g0 + kG2Flush, nst);
-    for (int st = g0; st < gend; ++st) {
-      load_tab(st0 + st + 3);
-      // inputs of stage st+1 (past the chunk end they produce unused values)
-      GenIn gin;
-      gen_read(tb0 + ((st + 1) % 3) * tbs, pr0 + ((st + 1) & 1) * prs, gin);
-      const __bf16* S = stg0 + (st & 1) * kGmStageElems;
-      bf16x8 aop[2][3], bop[2][3];
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-          bop[cb][q] = *reinterpret_cast<const bf16x8*>(
-              S + (q * kG2Slots + jslot + wc * 64 + cb * 32 + (lane & 31)) * kG2SlotPitch + (lane >> 5) * 8);
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-          aop[rb][q] = *reinterpret_cast<const bf16x8*>(
-              S + (q * kG2Slots + wr * 64 + rb * 32 + (lane & 31)) * kG2SlotPitch + (lane >> 5) * 8);
-      // six products, interleaved over the four accumulators
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][1], bop[cb][1], acc[rb][cb]);  // mid*mid
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][2], bop[cb][0], acc[rb][cb]);  // lo*hi
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][2], acc[rb][cb]);  // hi*lo
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][1], bop[cb][0], acc[rb][cb]);  // mid*hi
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][1], acc[rb][cb]);  // hi*mid
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][0], acc[rb][cb]);  // hi*hi
-      gen_store(gin, stg0 + ((st + 1) & 1) * kGmStageElems);
-      make_pre(tb0 + ((st + 2) % 3) * tbs, pr0 + (st & 1) * prs);
-      store_tab(tb0 + (st % 3) * tbs);
-      __syncthreads();
+    for (int st = g0; st < gend; st += 2) {
+      stage(st, treg0, treg1);
+      if (st + 1 < gend) stage(st + 1, treg1, treg0);
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -469,9 +488,7 @@ void launch_gram_mixed_table(const double* x, int64_t N, int p, int n, const dou
 
 void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const GramPlan& g, const double* tab,
                        const double* reg, float* part, float* tab32, double* A, hipStream_t s, Prof* prof) {
-  prof_mark(prof, GP_PH_GRAM, true, s);
   launch_gram_mixed_table(x, N, p, n, tab, tab32, s);
-  prof_mark(prof, GP_PH_GRAM, false, s);
   for (int ps = 0; ps < g.passes; ++ps) {
     const int split0 = ps * g.splits_per_pass;
     const int cnt = std::min(g.splits_per_pass, g.splits_total - split0);
