@@ -63,7 +63,7 @@ static void model_sizes(int64_t M, int precision, size_t* sz) {
   const size_t v[kModelRegions] = {kTabSize * 8, (size_t)M * 8, (size_t)M * 8, MM * 8, MM * 8, MM * 8,
                                    (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8, (size_t)M * 8,
                                    (size_t)M * 8, 64,
-                                   precision == GP_PREC_MIXED ? 2 * (size_t)M * linv_pitch((int)M) * 2 : 0,
+                                   precision == GP_PREC_MIXED ? 2 * (size_t)linv_rows((int)M) * linv_pitch((int)M) * 2 : 0,
                                    (size_t)M * 16, (size_t)pdesc_elems((int)M) * 4};
   for (int r = 0; r < kModelRegions; ++r) sz[r] = v[r];
 }

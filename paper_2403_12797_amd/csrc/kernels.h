@@ -82,6 +82,9 @@ void launch_axpy(double* w, const double* d, int M, hipStream_t s);
 // Split of L^-1 into two bf16 terms (mixed predict): pieces[q][M][P] with
 // row pitch P = linv_pitch(M) (multiple of 16, padding columns zero).
 __host__ __device__ inline int linv_pitch(int M) { return (M + 15) & ~15; }
+// Rows of each L^-1 term: M rounded up to 256 (padding rows zero), so that
+// 256-row slabs read without bounds tests.
+__host__ __device__ inline int linv_rows(int M) { return (M + 255) & ~255; }
 void launch_split_linv(const double* Linv, __bf16* pieces, int M, hipStream_t s);
 
 // a5 variance: var[i] = sigma^2 || L^-1 phi_*(x_i) ||^2

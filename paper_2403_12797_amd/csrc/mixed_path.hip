@@ -548,21 +548,22 @@ void launch_midx(int p, int n, int M, uint16_t* midx, hipStream_t s) {
 // pieces[0] = hi, pieces[1] = lo of L^-1 (row pitch P, padding zero), each
 // element first rounded to FP32.  One thread per pair of columns.
 __global__ void split_linv_kernel(const double* __restrict__ Li, __bf16* __restrict__ pieces, int M, int P) {
-  const int r = blockIdx.y;
+  const int r = blockIdx.y;   // 0 .. linv_rows(M) - 1; rows past M are zero
   const int c = (blockIdx.x * blockDim.x + threadIdx.x) * 2;
   if (c >= P) return;
-  const float a = c < M ? (float)Li[(int64_t)r * M + c] : 0.0f;
-  const float b = c + 1 < M ? (float)Li[(int64_t)r * M + c + 1] : 0.0f;
+  const float a = (r < M && c < M) ? (float)Li[(int64_t)r * M + c] : 0.0f;
+  const float b = (r < M && c + 1 < M) ? (float)Li[(int64_t)r * M + c + 1] : 0.0f;
   uint32_t h, l;
   split2(a, b, h, l);
-  const int64_t PP = (int64_t)M * P;
+  const int64_t PP = (int64_t)linv_rows(M) * P;
   *reinterpret_cast<uint32_t*>(pieces + (int64_t)r * P + c) = h;
   *reinterpret_cast<uint32_t*>(pieces + PP + (int64_t)r * P + c) = l;
 }
 
 void launch_split_linv(const double* Linv, __bf16* pieces, int M, hipStream_t s) {
   const int P = linv_pitch(M);
-  hipLaunchKernelGGL(split_linv_kernel, dim3(ceil_div(P / 2, 256), M), dim3(256), 0, s, Linv, pieces, M, P);
+  hipLaunchKernelGGL(split_linv_kernel, dim3(ceil_div(P / 2, 256), linv_rows(M)), dim3(256), 0, s, Linv, pieces, M,
+                     P);
 }
 
 // ================================================================ a5 mixed predict
@@ -610,33 +611,47 @@ int64_t predict_mixed_part_elems(int64_t Ns, int M, int* groups_out) {
   return g * Ns;
 }
 
-// Per-column descriptor of the prediction: bits 0..15 the 1-D table row of
-// the last factor, (p-1)*n + k; bits 16..31 the prefix row relative to the
-// first prefix of the column's stage of 16.  Columns M .. ceil16(M)-1 point
+// Per-column descriptor of the prediction, as LDS byte offsets for a
+// work-group of TN test points: .x the prefix row relative to the first
+// prefix of the column's stage of 16 (times TN*4), .y the 1-D table row of
+// the last factor, (p-1)*n + k (times TN*4).  Columns M .. ceil16(M)-1 point
 // at the zero row p*n.
-__global__ void pdesc_kernel(int p, int n, int M, uint32_t* __restrict__ pdesc) {
+__global__ void pdesc_kernel(int p, int n, int M, int TN, uint2* __restrict__ pdesc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int Mp = (int)ceil_div(M, kPmKC) * kPmKC;
   if (c >= Mp) return;
+  const uint32_t rb = (uint32_t)TN * 4;
   if (c >= M) {
-    pdesc[c] = (uint32_t)(p * n);
+    pdesc[c] = uint2{0u, (uint32_t)(p * n) * rb};
     return;
   }
   const int hrel = c / n - (c - c % kPmKC) / n;
-  pdesc[c] = ((uint32_t)hrel << 16) | (uint32_t)((p - 1) * n + c % n);
+  pdesc[c] = uint2{(uint32_t)hrel * rb, (uint32_t)((p - 1) * n + c % n) * rb};
 }
 
+static int predict_tn(int p, int n);
 void launch_pdesc(int p, int n, int M, uint32_t* pdesc, hipStream_t s) {
   const int Mp = (int)ceil_div(M, kPmKC) * kPmKC;
-  hipLaunchKernelGGL(pdesc_kernel, dim3(ceil_div(Mp, 256)), dim3(256), 0, s, p, n, M, pdesc);
+  hipLaunchKernelGGL(pdesc_kernel, dim3(ceil_div(Mp, 256)), dim3(256), 0, s, p, n, M, predict_tn(p, n),
+                     reinterpret_cast<uint2*>(pdesc));
 }
-int64_t pdesc_elems(int M) { return ceil_div(M, kPmKC) * kPmKC; }
+int64_t pdesc_elems(int M) { return 2 * ceil_div(M, kPmKC) * kPmKC; }
+
+// Prefix digit table kept in LDS when it has at most this many entries: for
+// every prefix hi and leading dimension j, the byte offset of its 1-D table
+// row (j*n + digit_j) in a TN-point table.
+constexpr int kPdigMax = 2048;
+__host__ __device__ inline int pm_pdig_entries(int p, int n, int M) {
+  const int e = (M / n) * (p - 1);
+  return e <= kPdigMax ? e : 0;
+}
 
 template <int TN, int P>
 __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     const double* __restrict__ xs, int64_t Ns, int n, int M, const double* __restrict__ tab,
-    const uint16_t* __restrict__ midx, const uint32_t* __restrict__ pdesc, const __bf16* __restrict__ lpieces,
+    const uint16_t* __restrict__ midx, const uint32_t* __restrict__ pdesc_words, const __bf16* __restrict__ lpieces,
     int rpg, double* __restrict__ part) {
+  const uint2* __restrict__ pdesc = reinterpret_cast<const uint2*>(pdesc_words);
   using C = PmCfg<TN>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smraw[];
   const int npr = pm_pre_rows(n);
@@ -644,13 +659,15 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   float* const pre0 = Tf + (P * n + 1) * TN;                                // [2][npr][TN]
   __bf16* const buf0 = reinterpret_cast<__bf16*>(pre0 + 2 * npr * TN);      // [2][PHI + LIN]
   double* const ssw = reinterpret_cast<double*>(buf0 + 2 * (C::PHI + C::LIN));  // [WR][TN]
+  uint32_t* const pdig = reinterpret_cast<uint32_t*>(ssw + C::WR * TN);     // [M/n][P-1] or empty
+  const int npd = pm_pdig_entries(P, n, M);
   const int64_t i0 = (int64_t)blockIdx.x * TN;
   const int RB = (M + kPmTR - 1) / kPmTR;
   const int rb0 = blockIdx.y * rpg, rb1 = min(rb0 + rpg, RB);
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wp = wv % C::WP, wr = wv / C::WP;
   const int LP = linv_pitch(M);
-  const int64_t PP = (int64_t)M * LP;
+  const int64_t PP = (int64_t)linv_rows(M) * LP;
 
   for (int u = t; u < TN * P; u += kPmThreads) {
     const int i = u % TN, j = u / TN;
@@ -664,6 +681,10 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   }
   for (int u = t; u < TN; u += kPmThreads) Tf[P * n * TN + u] = 0.0f;
   for (int u = t; u < C::WR * TN; u += kPmThreads) ssw[u] = 0.0;
+  for (int u = t; u < npd; u += kPmThreads) {
+    const int hi = u / (P > 1 ? P - 1 : 1), j = u - hi * (P > 1 ? P - 1 : 1);
+    pdig[u] = (uint32_t)midx[(int64_t)hi * n * 8 + j] * (TN * 4);
+  }
 
   auto nstages = [&](int rb) { return (int)ceil_div(min(rb * kPmTR + kPmTR, M), kPmKC); };
   auto advance = [&](int& rb, int& k) {
@@ -680,13 +701,19 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
       const int i = u % TN;
       int hi = hi0 + r;
       if (hi * n >= M) hi = 0;   // past the last column: never referenced
-      const uint4 dq = reinterpret_cast<const uint4*>(midx)[hi * n];
-      const uint32_t d[4] = {dq.x, dq.y, dq.z, dq.w};
       float v = 1.0f;
+      if (npd) {
+        const char* tfi = reinterpret_cast<const char*>(Tf + i);
 #pragma unroll
-      for (int j = 0; j < P - 1; ++j) {
-        const int row = (d[j >> 1] >> ((j & 1) * 16)) & 0xffff;
-        v *= Tf[row * TN + i];
+        for (int j = 0; j < P - 1; ++j) v *= *reinterpret_cast<const float*>(tfi + pdig[hi * (P - 1) + j]);
+      } else {
+        const uint4 dq = reinterpret_cast<const uint4*>(midx)[hi * n];
+        const uint32_t d[4] = {dq.x, dq.y, dq.z, dq.w};
+#pragma unroll
+        for (int j = 0; j < P - 1; ++j) {
+          const int row = (d[j >> 1] >> ((j & 1) * 16)) & 0xffff;
+          v *= Tf[row * TN + i];
+        }
       }
       dst[r * TN + i] = v;
     }
@@ -694,13 +721,15 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   // Phi_* of stage k: point gp, columns gq*CPT .. +CPT (gq wave-uniform)
   const int gp = t % TN;
   const int gq = __builtin_amdgcn_readfirstlane(t / TN);
+  const char* const tf_gp = reinterpret_cast<const char*>(Tf + gp);
   auto gen_read = [&](int k, const float* pre, float* ga, float* gb) {
-    const uint32_t* dsc = pdesc + k * kPmKC + gq * C::CPT;
+    const uint2* dsc = pdesc + __builtin_amdgcn_readfirstlane(k * kPmKC + gq * C::CPT);
+    const char* pre_gp = reinterpret_cast<const char*>(pre + gp);
 #pragma unroll
     for (int u = 0; u < C::CPT; ++u) {
-      const uint32_t d = dsc[u];
-      ga[u] = pre[(d >> 16) * TN + gp];
-      gb[u] = Tf[(d & 0xffff) * TN + gp];
+      const uint2 d = dsc[u];
+      ga[u] = *reinterpret_cast<const float*>(pre_gp + d.x);
+      gb[u] = *reinterpret_cast<const float*>(tf_gp + d.y);
     }
   };
   auto gen_store = [&](const float* ga, const float* gb, __bf16* phi) {
@@ -727,16 +756,16 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   };
   // L^-1 slab (rows r0..r0+255, columns c0..c0+15, both terms): 1024 uint4,
   // two per thread.  Rows past M read as zero; padding columns are zero.
+  // (stage columns stay inside the pitch LP, a multiple of 16 >= M)
+  const int lr_r = (t >> 1) & 255;
+  const __bf16* const lbase0 = lpieces + (int64_t)lr_r * LP + (t & 1) * 8;   // term 0 (t < 512)
+  const __bf16* const lbase1 = lbase0 + PP;                                   // term 1
+  // (rows are padded to a multiple of 256 with zeros; a look-ahead past the
+  // last row block re-reads the last one)
   auto lin_load = [&](int rb, int k, uint4* reg) {
-    const int c0 = k * kPmKC;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int q = t + u * kPmThreads;        // 0..1023
-      const int term = q >> 9, r = (q >> 1) & 255, half = q & 1;
-      const int row = rb * kPmTR + r, c = c0 + half * 8;
-      reg[u] = (row < M && c < LP) ? *reinterpret_cast<const uint4*>(lpieces + term * PP + (int64_t)row * LP + c)
-                                  : uint4{0u, 0u, 0u, 0u};
-    }
+    const int64_t off = (int64_t)min(rb, RB - 1) * kPmTR * LP + k * kPmKC;
+    reg[0] = *reinterpret_cast<const uint4*>(lbase0 + off);
+    reg[1] = *reinterpret_cast<const uint4*>(lbase1 + off);
   };
   auto lin_store = [&](__bf16* lin, const uint4* reg) {
 #pragma unroll
@@ -860,7 +889,8 @@ template <int TN>
 static size_t predict_lds_bytes(int p, int n) {
   using C = PmCfg<TN>;
   return ((size_t)(p * n + 1) + 2 * (size_t)pm_pre_rows(n)) * TN * sizeof(float) +
-         2 * (C::PHI + C::LIN) * sizeof(__bf16) + (size_t)C::WR * TN * sizeof(double);
+         2 * (C::PHI + C::LIN) * sizeof(__bf16) + (size_t)C::WR * TN * sizeof(double) +
+         (size_t)kPdigMax * sizeof(uint32_t);
 }
 
 // TN = 256 test points per work-group when its tables fit, else 128.

@@ -132,6 +132,8 @@ def test_factor_stages_multiblock(torch_cuda, ctx, seed, p, n, N):
     (8, 1, 40, 600, 100),     # long 1-D expansion
     (9, 8, 2, 1500, 200),     # p = 8, M = 256
     (10, 3, 11, 5000, 513),   # M = 1331 (several 256-tiles, ragged)
+    (11, 7, 3, 3000, 300),    # M = 2187: prediction reads prefix digits from global memory
+    (12, 2, 64, 4000, 300),   # M = 4096, 128 table rows: 128-point prediction tiles
 ])
 @pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED])
 def test_random_shapes(torch_cuda, ctx, seed, p, n, N, Ns, precision):
