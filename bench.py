@@ -165,6 +165,9 @@ def served_stream(torch, rate, seconds, warm=2.0):
             "mean_ms": float(lat.mean()), "points_per_s": pts / span,
             "failed": int(sum(1 for k in sel if status[k] != B.GP_OK)),
             "wall_s": t_end - t_start,
+            # time to serve every arrival / arrival window: > 1 means the offered
+            # load exceeds what the device sustains, and p99 grows with run length
+            "rho": (t_end - t_start) / (warm + seconds),
             "workload": "Poisson 200 req/s fit+predict, p~U{2..5}, n=6 (M<=7776), N log-U[1e3,5e5], "
                         "N* log-U[1e2,1e5], mixed precision, 4 stream slots"}
 
