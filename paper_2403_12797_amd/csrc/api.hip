@@ -242,7 +242,7 @@ void enqueue_fit_tail(gp_model* m, const double* x, const double* y, int64_t N, 
   prof_mark(pr, GP_PH_SOLVE, true, s);
   launch_lower_matvec(m->Linv, m->b, z, M, s);
   launch_lower_t_matvec(m->Linv, z, m->w, ltpart, M, s);
-  launch_phi_matvec(x, N, p, n, M, m->tab, m->w, y, resid, s);                 // y - Phi w
+  launch_phi_matvec(x, N, p, n, M, m->tab, m->midx, m->w, y, resid, s);                 // y - Phi w
   launch_phiT_vec(x, resid, N, p, n, M, m->tab, vpart, m->reg, m->w, r, s);    // Phi^T(y - Phi w) - reg*w
   launch_lower_matvec(m->Linv, r, z, M, s);
   launch_lower_t_matvec(m->Linv, z, d, ltpart, M, s);
@@ -285,7 +285,7 @@ void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* me
   } else {
     if (mean) {
       prof_mark(pr, GP_PH_PREDICT_MEAN, true, s);
-      launch_phi_matvec(xs, Ns, p, n, M, m->tab, m->w, nullptr, mean, s);
+      launch_phi_matvec(xs, Ns, p, n, M, m->tab, m->midx, m->w, nullptr, mean, s);
       prof_mark(pr, GP_PH_PREDICT_MEAN, false, s);
     }
     if (var) launch_predict_var_f64(xs, Ns, p, n, M, m->tab, m->Linv, s2, (double*)ws, var, s, pr);

@@ -17,9 +17,9 @@ struct EigArgs {
 void launch_eig_tables(const EigArgs& a, double* tab, double* lam, double* reg, int M, hipStream_t s);
 
 // out[i] = y ? y[i] - (Phi w)_i : (Phi w)_i, Phi generated on the fly from x
-// (the mean Phi_* w and the residual y - Phi w).
+// (the mean Phi_* w and the residual y - Phi w); midx is the multi-index table.
 void launch_phi_matvec(const double* x, int64_t N, int p, int n, int M, const double* tab,
-                       const double* w, const double* y, double* out, hipStream_t s);
+                       const uint16_t* midx, const double* w, const double* y, double* out, hipStream_t s);
 
 // out[m] = sum_i Phi[i,m] v[i] - (sub ? sub[m] * wsub[m] : 0), deterministic
 // two-pass reduction through `part` (see phiT_part_elems).

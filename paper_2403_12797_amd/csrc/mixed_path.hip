@@ -103,7 +103,7 @@ constexpr int kG2Slots = kGmT + kG2H;                       // 384 column slots 
 constexpr int kG2SlotPitch = kGmKC + 8;                     // bf16 per slot (16 samples + pad)
 constexpr int kG2TabPitch = kGmKC + 4;                      // floats per table / prefix row (16 + pad)
 constexpr int kGmChunk = 8192;                              // samples per FP32 partial
-constexpr int64_t kGmPartCap = 4ll << 30;                   // bytes of partials per pass
+constexpr int64_t kGmPartCap = 8ll << 30;                   // bytes of partials per pass
 constexpr int kGmStageElems = 3 * kG2Slots * kG2SlotPitch;  // bf16 per stage buffer
 
 GramPlan gram_mixed_plan(int64_t N, int M, int chunk) {
@@ -462,19 +462,51 @@ __global__ void reset_counter_kernel(int* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
 
-__global__ void gram_mixed_reduce_kernel(const float* __restrict__ part, int splits, int T, int M,
-                                         const double* __restrict__ reg, int first, double* __restrict__ A) {
-  const int h = blockIdx.x * blockDim.x + threadIdx.x;
-  const int g = blockIdx.y;
-  if (h >= M || h < g) return;
-  const int I = g / kGmT, J = h / kGmT;
+// One 64x64 tile of the upper triangle per work-group: each element sums
+// its splits in split order in FP64 (256 threads, 16 elements each), then
+// the tile is written to A and, transposed through LDS, to its mirror
+// image, both with row-contiguous stores.
+__global__ void __launch_bounds__(256) gram_mixed_reduce_kernel(const float* __restrict__ part, int splits, int T,
+                                                                int M, const double* __restrict__ reg, int first,
+                                                                double* __restrict__ A) {
+  __shared__ double tr[64][65];
+  const int T64 = (M + 63) / 64;
+  int t = blockIdx.x, R = 0;                 // upper-triangle 64-tile (R, C), C >= R
+  while (t >= T64 - R) {
+    t -= T64 - R;
+    ++R;
+  }
+  const int C = R + t;
+  const int g0 = R * 64, h0 = C * 64;
+  const int I = g0 / kGmT, J = h0 / kGmT;    // the 256-tile holding this 64-tile
   const int ti = I * T - I * (I - 1) / 2 + (J - I);
-  const int ntiles = T * (T + 1) / 2;
-  const int64_t off = (int64_t)ti * kGmT * kGmT + (int64_t)(g - I * kGmT) * kGmT + (h - J * kGmT);
-  double s = first ? (g == h ? reg[g] : 0.0) : A[(int64_t)g * M + h];
-  for (int k = 0; k < splits; ++k) s += (double)part[(int64_t)k * ntiles * kGmT * kGmT + off];
-  A[(int64_t)g * M + h] = s;
-  A[(int64_t)h * M + g] = s;
+  const int64_t ntile = (int64_t)(T * (T + 1) / 2) * kGmT * kGmT;
+  const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int h = h0 + c;
+  double s[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int g = g0 + r0 + 4 * q;
+    s[q] = first ? ((g == h && g < M) ? reg[g] : 0.0) : ((g < M && h < M) ? A[(int64_t)g * M + h] : 0.0);
+  }
+  const int64_t base = (int64_t)ti * kGmT * kGmT + (int64_t)(g0 - I * kGmT) * kGmT + (h0 - J * kGmT) + c;
+  for (int k = 0; k < splits; ++k) {
+    const float* pk = part + (int64_t)k * ntile + base;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s[q] += (double)pk[(int64_t)(r0 + 4 * q) * kGmT];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int g = g0 + r0 + 4 * q;
+    if (g < M && h < M && h >= g) A[(int64_t)g * M + h] = s[q];
+    tr[r0 + 4 * q][c] = s[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int hh = h0 + r0 + 4 * q, gg = g0 + c;   // A[hh][gg] = A[gg][hh]
+    if (hh < M && gg < M && hh > gg) A[(int64_t)hh * M + gg] = tr[c][r0 + 4 * q];
+  }
 }
 
 size_t gram_mixed_lds_bytes(int p, int n, int M) { return gram_lds_bytes(p, n, M); }
@@ -504,7 +536,8 @@ void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const Gr
 
 void launch_gram_mixed_reduce(const float* part, int splits, int T, int M, const double* reg, bool first, double* A,
                               hipStream_t s) {
-  hipLaunchKernelGGL(gram_mixed_reduce_kernel, dim3(ceil_div(M, 256), M), dim3(256), 0, s, part, splits, T, M, reg,
+  const int T64 = (int)ceil_div(M, 64);
+  hipLaunchKernelGGL(gram_mixed_reduce_kernel, dim3(T64 * (T64 + 1) / 2), dim3(256), 0, s, part, splits, T, M, reg,
                      first ? 1 : 0, A);
 }
 
@@ -921,7 +954,7 @@ void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, con
   if (Ns <= 0) return;
   if (mean) {
     prof_mark(prof, GP_PH_PREDICT_MEAN, true, s);
-    launch_phi_matvec(xs, Ns, p, n, M, tab, w, nullptr, mean, s);
+    launch_phi_matvec(xs, Ns, p, n, M, tab, midx, w, nullptr, mean, s);
     prof_mark(prof, GP_PH_PREDICT_MEAN, false, s);
   }
   if (!var) return;

@@ -102,8 +102,21 @@ __device__ __forceinline__ void fill_tab_cf(const double* __restrict__ x, int64_
 // fixed order.
 constexpr int kMvRows = 64;
 
+__device__ __forceinline__ f64x4 mfma64m(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Phi w (or y - Phi w) for a block of 64 samples, on FP64 MFMA.  With
+// m = hi*n + k (k the last digit) Phi[i, m] = PRE[i][hi] * phi_{p-1,k}(x_i), so
+//   (Phi w)[i] = sum_hi PRE[i][hi] * U[i][hi],  U = Lt Wm,
+// Lt[i][k] = phi_{p-1,k}(x_i) (64 x n), Wm[k][hi] = w[hi*n + k] (n x M/n).
+// Each wave takes prefix tiles of 16 (tile wv, wv+4, ...) against all 64
+// samples (four 16-row MFMA tiles, k padded to 4), scales U by the prefix
+// products of its lanes' (sample, prefix) pairs and accumulates per sample;
+// the 16 lanes of a sample and then the four waves are summed at the end.
 __global__ void __launch_bounds__(256) phi_matvec_kernel(const double* __restrict__ x, int64_t N, int p,
                                                          int n, int M, const double* __restrict__ tab,
+                                                         const uint16_t* __restrict__ midx,
                                                          const double* __restrict__ w,
                                                          const double* __restrict__ y,
                                                          double* __restrict__ out) {
@@ -114,23 +127,59 @@ __global__ void __launch_bounds__(256) phi_matvec_kernel(const double* __restric
   fill_tab_sf<double>(x, N, p, n, s0, kMvRows, kMvRows, tab, T);
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int nhi = M / n;
-  double acc = 0.0;
-  int dig[GP_MAX_P];
-  for (int hi = wv; hi < nhi; hi += 4) {
-    // prefix product over dims 0..p-2 (digits of hi)
-    int rem = hi;
-    for (int j = p - 2; j >= 0; --j) {
-      dig[j] = rem % n;
-      rem /= n;
+  const int H = M / n, nk = (n + 3) / 4;
+  const double* Tl = T + (p - 1) * n * kMvRows;   // rows of the last factor
+  double acc[4][4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[rt][q] = 0.0;
+  for (int ht = wv; ht * 16 < H; ht += 4) {
+    const int hi = ht * 16 + (lane & 15);
+    const bool hv = hi < H;
+    f64x4 d[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) d[rt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int ks = 0; ks < nk; ++ks) {
+      const int k = ks * 4 + (lane >> 4);
+      const bool kv = k < n;
+      const double b = (hv && kv) ? w[(int64_t)hi * n + k] : 0.0;
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        const double a = kv ? Tl[k * kMvRows + rt * 16 + (lane & 15)] : 0.0;
+        d[rt] = mfma64m(a, b, d[rt]);
+      }
     }
-    double pre = 1.0;
-    for (int j = 0; j < p - 1; ++j) pre *= T[(j * n + dig[j]) * kMvRows + lane];
-    const double* Tl = T + ((p - 1) * n) * kMvRows + lane;
-    const double* wl = w + (int64_t)hi * n;
-    for (int k = 0; k < n; ++k) acc = fma(pre * Tl[k * kMvRows], wl[k], acc);
+    // 1-D table rows of the leading digits of this lane's prefix
+    int rows[GP_MAX_P];
+    {
+      const uint4 dq = reinterpret_cast<const uint4*>(midx)[hv ? hi * n : 0];
+      const uint32_t dd[4] = {dq.x, dq.y, dq.z, dq.w};
+#pragma unroll
+      for (int j = 0; j < GP_MAX_P; ++j) rows[j] = (dd[j >> 1] >> ((j & 1) * 16)) & 0xffff;
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int sm_i = rt * 16 + 4 * q + (lane >> 4);
+        double pre = hv ? 1.0 : 0.0;
+        for (int j = 0; j < p - 1; ++j) pre *= T[rows[j] * kMvRows + sm_i];
+        acc[rt][q] = fma(pre, d[rt][q], acc[rt][q]);
+      }
   }
-  red[wv * kMvRows + lane] = acc;
+  // sum over the 16 lanes that share a sample, then over the waves
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double v = acc[rt][q];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      if ((lane & 15) == 0) red[wv * kMvRows + rt * 16 + 4 * q + (lane >> 4)] = v;
+    }
   __syncthreads();
   if (wv == 0) {
     const double sum = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
@@ -139,11 +188,11 @@ __global__ void __launch_bounds__(256) phi_matvec_kernel(const double* __restric
   }
 }
 
-void launch_phi_matvec(const double* x, int64_t N, int p, int n, int M, const double* tab,
+void launch_phi_matvec(const double* x, int64_t N, int p, int n, int M, const double* tab, const uint16_t* midx,
                        const double* w, const double* y, double* out, hipStream_t s) {
   if (N <= 0) return;
   const size_t lds = (size_t)(p * n * kMvRows + 4 * kMvRows) * sizeof(double);
-  hipLaunchKernelGGL(phi_matvec_kernel, dim3(ceil_div(N, kMvRows)), dim3(256), lds, s, x, N, p, n, M, tab,
+  hipLaunchKernelGGL(phi_matvec_kernel, dim3(ceil_div(N, kMvRows)), dim3(256), lds, s, x, N, p, n, M, tab, midx,
                      w, y, out);
 }
 
