@@ -1,6 +1,8 @@
 """Benchmark: train+test points/s of one fit + predict (mean and variance) of
-the Mercer GP on one MI355X, split-BF16 mixed path beside the plain FP64 GPU
-path, plus the FP64 CPU oracle on a bounded sample of the same workload.
+the Mercer GP on one MI355X: the mixed path (Gram as split-FP16 MFMA on scaled
+Phi by default, or as split-BF16 with --gram bf16), the other Gram scheme and
+the plain FP64 GPU path beside it, plus the FP64 CPU oracle on a bounded
+sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -24,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "train+test points/s at p=4,M=4096 (mixed vs FP64 GPU); p50/p99 request latency"
-PEAK_BF16 = 2.5e15      # dense MFMA, MI355X
+PEAK_16 = 2.5e15        # dense FP16 / BF16 MFMA, MI355X
 PEAK_FP64 = 78.6e12     # FP64 MFMA, MI355X
 
 
@@ -36,6 +38,10 @@ def parse():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--N", type=int, default=None)
     ap.add_argument("--Ns", type=int, default=None)
+    ap.add_argument("--gram", choices=("f16", "bf16"), default="f16",
+                    help="Gram scheme of the timed mixed path: two FP16 terms (3 products) or three BF16 terms "
+                         "(6 products)")
+    ap.add_argument("--no-alt", action="store_true", help="skip timing the other Gram scheme")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-target-s", type=float, default=15.0)
@@ -77,7 +83,7 @@ def served_stream(torch, rate, seconds, warm=2.0):
     """Poisson arrivals of fit+predict requests through gp_submit / gp_poll:
     p ~ U{2..5}, n = 6, N log-U[1e3, 5e5], N* log-U[1e2, 1e5], x ~ U[-1,1]^p,
     y = exp(-|x|^2) + cos(3 x1 x2) + N(0, 0.05^2), sigma = 0.05, eps = 1,
-    alpha = 1.2, mixed precision.  Inputs are slices of seeded device-resident
+    alpha = 1.2, mixed precision (FP16 Gram).  Inputs are slices of seeded device-resident
     pools (drawn before the stream starts).  Returns latency percentiles and
     sustained points/s over the requests that arrived after the warm-up."""
     import threading
@@ -106,7 +112,7 @@ def served_stream(torch, rate, seconds, warm=2.0):
         reqs.append((t, p, N, Ns, off, offs))
     torch.cuda.synchronize()
     ctx = B.Context(0)
-    prm = {p: B.make_params(p, 6, 0.05, 1.0, 1.2, B.PREC_MIXED) for p in range(2, 6)}
+    prm = {p: B.make_params(p, 6, 0.05, 1.0, 1.2, B.PREC_MIXED_F16) for p in range(2, 6)}
     means = [torch.empty(r[3], dtype=torch.float64, device="cuda") for r in reqs]
     vars_ = [torch.empty(r[3], dtype=torch.float64, device="cuda") for r in reqs]
     ids = [None] * len(reqs)
@@ -169,7 +175,7 @@ def served_stream(torch, rate, seconds, warm=2.0):
             # load exceeds what the device sustains, and p99 grows with run length
             "rho": (t_end - t_start) / (warm + seconds),
             "workload": "Poisson 200 req/s fit+predict, p~U{2..5}, n=6 (M<=7776), N log-U[1e3,5e5], "
-                        "N* log-U[1e2,1e5], mixed precision, 4 stream slots"}
+                        "N* log-U[1e2,1e5], mixed precision (FP16 Gram), 4 stream slots"}
 
 
 def cpu_baseline(P_full, target_s):
@@ -211,7 +217,7 @@ def gram_source_fingerprint():
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def gram_traffic(P, launches_per_step):
+def gram_traffic(P, scheme):
     """HBM bytes per Gram launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE record, scaled by the copy-kernel calibration; None when the
     record is for another workload or the kernel source has changed since."""
@@ -220,8 +226,8 @@ def gram_traffic(P, launches_per_step):
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None, "no counter record"
-    if rec.get("N") != P.N or rec.get("M") != P.M or rec.get("workload") != P.name:
-        return None, "counter record is for another workload"
+    if rec.get("N") != P.N or rec.get("M") != P.M or rec.get("workload") != P.name or rec.get("gram") != scheme:
+        return None, "counter record is for another workload or Gram scheme"
     if rec.get("source_fingerprint") != gram_source_fingerprint():
         return None, "kernel changed since the counters were taken"
     kib = sum(rec["fetch_kib_per_launch"]) * rec["fetch_factor"] + sum(rec["write_kib_per_launch"]) * rec["write_factor"]
@@ -253,9 +259,19 @@ def main():
     dev = tuple(torch.from_numpy(np.ascontiguousarray(v)).cuda() for v in (P.x, P.y, P.xs))
     torch.cuda.synchronize()
     ctx = B.Context(0)
-    print(f"[bench] {P.name} N={P.N} Ns={P.Ns} M={P.M}: mixed path", file=sys.stderr, flush=True)
-    dt_mx, prof_mx, _ = run_path(ctx, torch, P, dev, B.PREC_MIXED, a.steps, a.warmup)
+    f16 = a.gram == "f16"
+    prec = B.PREC_MIXED_F16 if f16 else B.PREC_MIXED
+    print(f"[bench] {P.name} N={P.N} Ns={P.Ns} M={P.M}: mixed path, {a.gram} Gram", file=sys.stderr, flush=True)
+    dt_mx, prof_mx, _ = run_path(ctx, torch, P, dev, prec, a.steps, a.warmup)
     print(f"[bench] mixed {dt_mx * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    alt = None
+    if not a.no_alt:
+        k_alt = max(1, min(a.steps, 2))
+        dt_alt, prof_alt, _ = run_path(ctx, torch, P, dev, B.PREC_MIXED if f16 else B.PREC_MIXED_F16, k_alt, 1)
+        print(f"[bench] other Gram scheme {dt_alt * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+        alt = {"gram": "bf16x3 (3 terms, 6 products)" if f16 else "f16x2 (2 terms, 3 products)",
+               "value": (P.N + P.Ns) / dt_alt, "ms_per_step": dt_alt * 1e3, "steps": k_alt,
+               "phases_ms": {k: round(v[0] / k_alt, 3) for k, v in prof_alt.items() if v[1]}}
     fp64 = None
     if not a.no_fp64:
         k64 = max(1, min(a.steps, 2))
@@ -273,26 +289,30 @@ def main():
     avg_launch_ms = g_ms / g_cnt
     flops_per_step = P.N * P.M * (P.M + 1)            # useful Gram flops (upper triangle, mul+add)
     achieved = flops_per_step / (g_ms / steps * 1e-3)
-    issued = 6.0 * achieved * (2.0 * 65536 * (((P.M + 255) // 256) * ((P.M + 255) // 256 + 1) // 2)) / \
+    issued = (3.0 if f16 else 6.0) * achieved * (2.0 * 65536 * (((P.M + 255) // 256) * ((P.M + 255) // 256 + 1) // 2)) / \
         (P.M * (P.M + 1))
     pv_ms = prof_mx["predict"][0] / steps
-    traffic, traffic_note = gram_traffic(P, launches_per_step)
+    traffic, traffic_note = gram_traffic(P, a.gram)
     out = {
         "metric": METRIC, "value": (P.N + P.Ns) / dt_mx, "unit": "points/s", "n_gpus": 1, "steps": steps,
         "warmup": a.warmup, "ms_per_step": dt_mx * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "vs_baseline": None, "dtype": ("f16x2 Gram" if f16 else "bf16x3 Gram") + ", bf16x2 variance, fp32 acc, fp64 factor",
+        "data": "synthetic",
         "config": {"workload": f"{P.name}: p={P.p}, n={P.n}, M={P.M}, N={P.N}, N*={P.Ns}, "
                                f"x~U[-1,1]^4, y=exp(-|x|^2)+cos(3x1x2)+N(0,0.05^2), eps=1, alpha=1.2; "
-                               f"fit + predict(mean, var), split-BF16 MFMA (3 terms, 6 products Gram; "
-                               f"2 terms, 3 products variance), FP64 Cholesky + 1 refinement",
-                   "precision": "mixed"},
-        "roofline": {"kernel": "gram_mixed_kernel", "bound": "mfma", "achieved": achieved / 1e12,
-                     "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_BF16,
+                               f"fit + predict(mean, var); Gram "
+                               + ("split-FP16 MFMA on power-of-two-scaled Phi (2 terms, 3 products)" if f16 else
+                                  "split-BF16 MFMA (3 terms, 6 products)")
+                               + "; variance split-BF16 MFMA (2 terms, 3 products); FP64 Cholesky + 1 refinement",
+                   "precision": "mixed_f16" if f16 else "mixed"},
+        "roofline": {"kernel": f"gram_mixed_kernel<{'true' if f16 else 'false'}>", "bound": "mfma", "achieved": achieved / 1e12,
+                     "peak": PEAK_16 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_16,
                      "traffic": traffic, "traffic_note": traffic_note, "launches_per_step": launches_per_step,
                      "avg_launch_ms": avg_launch_ms, "algorithmic_flops_per_step": flops_per_step,
-                     "mfma_issue_frac": issued / PEAK_BF16,
-                     "predict_kernel_frac": (P.Ns * P.M * (P.M + 1)) / (pv_ms * 1e-3) / PEAK_BF16},
+                     "mfma_issue_frac": issued / PEAK_16,
+                     "predict_kernel_frac": (P.Ns * P.M * (P.M + 1)) / (pv_ms * 1e-3) / PEAK_16},
         "phases_ms": {k: round(v[0] / steps, 3) for k, v in prof_mx.items() if v[1]},
+        "other_gram_scheme": alt,
         "fp64_path": fp64,
         "served": None,
         "cpu_baseline": None if a.no_cpu else cpu_baseline(P, a.cpu_target_s),

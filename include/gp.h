@@ -53,10 +53,19 @@ typedef enum {
 } gp_status;
 
 typedef enum {
-  GP_PREC_FP64 = 0,    /* every contraction in FP64 (FP64 MFMA)                 */
-  GP_PREC_MIXED = 1    /* Gram / predict as split-BF16 MFMA products with FP32
-                          accumulation; FP64 factorisation, solves, one FP64
-                          iterative-refinement step on w                         */
+  GP_PREC_FP64 = 0,      /* every contraction in FP64 (FP64 MFMA)               */
+  GP_PREC_MIXED = 1,     /* Gram as split-BF16 MFMA products (three BF16 terms
+                            per value, six products), predictive variance as
+                            split-BF16 (two terms, three products), FP32
+                            accumulation; FP64 factorisation, solves, one FP64
+                            iterative-refinement step on w                     */
+  GP_PREC_MIXED_F16 = 2  /* as GP_PREC_MIXED, but the Gram as split-FP16 MFMA
+                            products (two FP16 terms per value, three
+                            products) on Phi scaled by exact powers of two per
+                            1-D table row.  The FP16 pair keeps about 22
+                            significant bits per value (the BF16 triple keeps
+                            all 24 of FP32) at half the matrix work; the
+                            same tolerances hold for both                      */
 } gp_precision;
 
 /* Limits enforced by validation. */

@@ -17,7 +17,7 @@ GP_OK, GP_PENDING = 0, 1
 GP_EINVAL, GP_ENOMEM, GP_ENOTSPD, GP_EDEVICE, GP_ENOTFOUND, GP_ECANCELED = -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "GP_OK", 1: "GP_PENDING", -1: "GP_EINVAL", -2: "GP_ENOMEM", -3: "GP_ENOTSPD",
                 -4: "GP_EDEVICE", -5: "GP_ENOTFOUND", -6: "GP_ECANCELED"}
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_MIXED_F16 = 0, 1, 2
 MODEL_W, MODEL_LAMBDA, MODEL_A, MODEL_B, MODEL_L, MODEL_LINV = range(6)
 REQ_FIT, REQ_PREDICT, REQ_FIT_PREDICT = 0, 1, 2
 MAX_P, MAX_N, MAX_M = 8, 64, 16384
@@ -198,12 +198,16 @@ class Context:
         return c.value
 
     def fit_batch(self, problems, precision=PREC_MIXED, stream=None):
-        """problems: list of (x, y, p, n, sigma, eps, alpha) with device x, y."""
+        """problems: list of (x, y, p, n, sigma, eps, alpha) with device x, y;
+        precision: one gp_precision for all, or one per problem."""
         k = len(problems)
+        precs = [precision] * k if isinstance(precision, int) else list(precision)
+        if len(precs) != k:
+            raise ValueError("precision: one value or one per problem")
         prms = (GpParams * k)()
         keep = []
         for i, (x, y, p, n, sigma, eps, alpha) in enumerate(problems):
-            prm = make_params(p, n, sigma, eps, alpha, precision)
+            prm = make_params(p, n, sigma, eps, alpha, precs[i])
             keep.append(prm._keep)
             prms[i] = prm
         xs = (C.c_void_p * k)(*[_ptr(pr[0]).value for pr in problems])

@@ -48,7 +48,7 @@ gp_status validate_params(const gp_params* prm, int64_t* M_out) {
     if (!(prm->alpha[j] > 0.0) || !isfinite(prm->alpha[j]))
       return fail(GP_EINVAL, "alpha[%d] must be finite and > 0", j);
   }
-  if (prm->precision != GP_PREC_FP64 && prm->precision != GP_PREC_MIXED)
+  if (prm->precision != GP_PREC_FP64 && !prec_mixed(prm->precision))
     return fail(GP_EINVAL, "unknown precision %d", prm->precision);
   *M_out = M;
   return GP_OK;
@@ -63,7 +63,7 @@ static void model_sizes(int64_t M, int precision, size_t* sz) {
   const size_t v[kModelRegions] = {kTabSize * 8, (size_t)M * 8, (size_t)M * 8, MM * 8, MM * 8, MM * 8,
                                    (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8, (size_t)M * 8,
                                    (size_t)M * 8, 64,
-                                   precision == GP_PREC_MIXED ? 2 * (size_t)linv_rows((int)M) * linv_pitch((int)M) * 2 : 0,
+                                   prec_mixed(precision) ? 2 * (size_t)linv_rows((int)M) * linv_pitch((int)M) * 2 : 0,
                                    (size_t)M * 16, (size_t)pdesc_elems((int)M) * 4};
   for (int r = 0; r < kModelRegions; ++r) sz[r] = v[r];
 }
@@ -84,7 +84,7 @@ FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chun
     o += align_up(bytes);
     return r;
   };
-  if (precision == GP_PREC_MIXED) {
+  if (prec_mixed(precision)) {
     L.g = gram_mixed_plan(N, (int)M, chunk);
     if (all_splits) L.g.splits_per_pass = L.g.splits_total, L.g.passes = 1;
     L.gpart = take((size_t)gram_mixed_part_elems(L.g) * 4);
@@ -110,7 +110,7 @@ size_t fit_workspace_bytes(gp_ctx* ctx, int64_t N, int p, int n, int64_t M, int 
 
 size_t predict_workspace_bytes(int64_t Ns, int64_t M, int precision) {
   if (Ns <= 0) return 0;
-  return (precision == GP_PREC_MIXED ? (size_t)predict_mixed_part_elems(Ns, (int)M, nullptr)
+  return (prec_mixed(precision) ? (size_t)predict_mixed_part_elems(Ns, (int)M, nullptr)
                                      : (size_t)predict_part_elems(Ns, (int)M, nullptr)) *
              8 +
          256;
@@ -185,7 +185,7 @@ gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t 
   m->w = (double*)take(sizes[7]);
   m->b = (double*)take(sizes[8]);
   m->flags = (int*)take(sizes[9]);
-  m->linv_pieces = prm->precision == GP_PREC_MIXED ? (__bf16*)take(sizes[10]) : nullptr;
+  m->linv_pieces = prec_mixed(prm->precision) ? (__bf16*)take(sizes[10]) : nullptr;
   m->midx = (uint16_t*)take(sizes[11]);
   m->pdesc = (uint32_t*)take(sizes[12]);
   *out = m;
@@ -212,8 +212,8 @@ void enqueue_fit_head(gp_model* m, const double* x, const double* y, int64_t N, 
   launch_check_finite(y, N, m->flags + 1, s);
   launch_eig_tables(a, m->tab, m->lam, m->reg, M, s);
   launch_midx(p, n, M, m->midx, s);
-  if (m->precision == GP_PREC_MIXED) launch_pdesc(p, n, M, m->pdesc, s);
-  if (m->precision == GP_PREC_MIXED) launch_gram_mixed_table(x, N, p, n, m->tab, (float*)(wb + L.tab32), s);
+  if (prec_mixed(m->precision)) launch_pdesc(p, n, M, m->pdesc, s);
+  if (prec_mixed(m->precision)) launch_gram_mixed_table(x, N, p, n, m->tab, (float*)(wb + L.tab32), s);
 }
 
 // tail: b = Phi^T y, Cholesky, L^-1, w with one FP64 refinement step, BF16 split.
@@ -248,7 +248,7 @@ void enqueue_fit_tail(gp_model* m, const double* x, const double* y, int64_t N, 
   launch_lower_t_matvec(m->Linv, z, d, ltpart, M, s);
   launch_axpy(m->w, d, M, s);
   prof_mark(pr, GP_PH_SOLVE, false, s);
-  if (m->precision == GP_PREC_MIXED) {
+  if (prec_mixed(m->precision)) {
     prof_mark(pr, GP_PH_SPLIT, true, s);
     launch_split_linv(m->Linv, m->linv_pieces, M, s);
     prof_mark(pr, GP_PH_SPLIT, false, s);
@@ -264,9 +264,9 @@ void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void*
   Prof* pr = &m->ctx->prof;
   enqueue_fit_head(m, x, y, N, L, ws, s);
   // a3: A = Phi^T Phi + sigma^2 Lambda^-1
-  if (m->precision == GP_PREC_MIXED) {
-    launch_gram_mixed(x, N, p, n, M, L.g, m->tab, m->reg, (float*)(wb + L.gpart), (float*)(wb + L.tab32), m->A, s,
-                      pr);
+  if (prec_mixed(m->precision)) {
+    launch_gram_mixed(x, N, p, n, M, L.g, m->precision == GP_PREC_MIXED_F16, m->tab, m->reg, (float*)(wb + L.gpart),
+                      (float*)(wb + L.tab32), m->A, s, pr);
   } else {
     launch_gram_f64(x, N, p, n, M, m->tab, m->reg, (double*)(wb + L.gpart), m->A, s, pr);
   }
@@ -279,7 +279,7 @@ void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* me
   const int p = m->p, n = m->n, M = (int)m->M;
   const double s2 = m->sigma * m->sigma;
   Prof* pr = &m->ctx->prof;
-  if (m->precision == GP_PREC_MIXED) {
+  if (prec_mixed(m->precision)) {
     launch_predict_mixed(xs, Ns, p, n, M, m->tab, m->midx, m->pdesc, m->linv_pieces, m->w, s2, (double*)ws, mean,
                          var, s, pr);
   } else {

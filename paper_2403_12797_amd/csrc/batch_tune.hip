@@ -2,7 +2,7 @@
 // autotuner.
 //
 // gp_fit_batch: every problem's eigen tables and 1-D tables, then ONE
-// persistent split-BF16 Gram launch over the work items of all mixed
+// persistent Gram launch per split scheme over the work items of all mixed
 // problems (longest first, pulled through an atomic counter), then each
 // problem's reduction, Cholesky, L^-1, solves and refinement on forked
 // streams.  The whole sequence is captured into a HIP graph and launched
@@ -76,7 +76,7 @@ gp_status gp_autotune(gp_ctx* ctx, int32_t p, int32_t n, int64_t N, int32_t* chu
   if (!ctx) return fail(GP_EINVAL, "ctx is NULL");
   double one[GP_MAX_P];
   for (int j = 0; j < GP_MAX_P; ++j) one[j] = 1.0;
-  gp_params prm{p, n, 0.1, one, one, GP_PREC_MIXED};
+  gp_params prm{p, n, 0.1, one, one, GP_PREC_MIXED_F16};
   int64_t M = 0;
   gp_status st = validate_params(&prm, &M);
   if (st != GP_OK) return st;
@@ -111,6 +111,7 @@ gp_status gp_autotune(gp_ctx* ctx, int32_t p, int32_t n, int64_t N, int32_t* chu
   a.sigma = 0.1;
   for (int j = 0; j < p; ++j) a.eps[j] = a.alpha[j] = 1.0;
   launch_eig_tables(a, tab, lam, reg, (int)M, s);
+  launch_gram_mixed_table(x, N, p, n, tab, tab32, s);
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
@@ -123,7 +124,7 @@ gp_status gp_autotune(gp_ctx* ctx, int32_t p, int32_t n, int64_t N, int32_t* chu
     float tot = 0.0f;
     for (int rep = 0; rep < 3; ++rep) {
       hipEventRecord(e0, s);
-      launch_gram_mixed(x, N, p, n, (int)M, g, tab, reg, part, tab32, A, s, nullptr);
+      launch_gram_mixed(x, N, p, n, (int)M, g, true, tab, reg, part, tab32, A, s, nullptr);
       hipEventRecord(e1, s);
       hipEventSynchronize(e1);
       float ms = 0.0f;
@@ -180,36 +181,42 @@ gp_status gp_fit_batch(gp_ctx* ctx, int32_t count, const gp_params* params, cons
     off[k] = total;
     total += (Ls[k].total + 255) & ~(size_t)255;
   }
-  // batched Gram work list (mixed problems)
+  // batched Gram work lists of the mixed problems, one per Gram scheme
+  // (FP16 items first, then BF16), each longest first
   std::vector<GramProb> probs;
   std::vector<GramItem> items;
   std::vector<int> prob_of(count, -1);
-  size_t lds = 0;
-  for (int k = 0; k < count; ++k) {
-    if (params[k].precision != GP_PREC_MIXED) continue;
-    const GramPlan& g = Ls[k].g;
-    prob_of[k] = (int)probs.size();
-    GramProb gp{};
-    gp.N = N[k];
-    gp.p = params[k].p;
-    gp.n = params[k].n;
-    gp.M = (int)Ms[k];
-    gp.T = g.T;
-    gp.chunk = g.chunk;
-    probs.push_back(gp);
-    lds = std::max(lds, gram_mixed_lds_bytes(params[k].p, params[k].n, (int)Ms[k]));
-    for (int sp = 0; sp < g.splits_total; ++sp)
-      for (int t = 0; t < g.ntiles; ++t)
-        for (int h = 0; h < 2; ++h) items.push_back(GramItem{prob_of[k], t, h, sp});
+  size_t lds[2] = {0, 0};
+  int nsch[2] = {0, 0};
+  for (int sch = 0; sch < 2; ++sch) {
+    const size_t first = items.size();
+    for (int k = 0; k < count; ++k) {
+      if (params[k].precision != (sch == 0 ? GP_PREC_MIXED_F16 : GP_PREC_MIXED)) continue;
+      const GramPlan& g = Ls[k].g;
+      prob_of[k] = (int)probs.size();
+      GramProb gp{};
+      gp.N = N[k];
+      gp.p = params[k].p;
+      gp.n = params[k].n;
+      gp.M = (int)Ms[k];
+      gp.T = g.T;
+      gp.chunk = g.chunk;
+      probs.push_back(gp);
+      lds[sch] = std::max(lds[sch], gram_mixed_lds_bytes(params[k].p, params[k].n, (int)Ms[k], sch == 0));
+      for (int sp = 0; sp < g.splits_total; ++sp)
+        for (int t = 0; t < g.ntiles; ++t)
+          for (int h = 0; h < 2; ++h) items.push_back(GramItem{prob_of[k], t, h, sp});
+    }
+    // longest first: full chunks before each problem's shorter last chunk
+    std::stable_sort(items.begin() + first, items.end(), [&](const GramItem& a, const GramItem& b) {
+      auto len = [&](const GramItem& i) {
+        const GramProb& q = probs[i.prob];
+        return std::min<int64_t>(q.chunk, q.N - (int64_t)i.split * q.chunk);
+      };
+      return len(a) > len(b);
+    });
+    nsch[sch] = (int)(items.size() - first);
   }
-  // longest first: full chunks before each problem's shorter last chunk
-  std::stable_sort(items.begin(), items.end(), [&](const GramItem& a, const GramItem& b) {
-    auto len = [&](const GramItem& i) {
-      const GramProb& q = probs[i.prob];
-      return std::min<int64_t>(q.chunk, q.N - (int64_t)i.split * q.chunk);
-    };
-    return len(a) > len(b);
-  });
   const size_t meta = probs.size() * sizeof(GramProb) + items.size() * sizeof(GramItem) + 256;
   char* ws = nullptr;
   hipError_t e = hipMallocAsync((void**)&ws, total + meta + 512, s);
@@ -257,15 +264,17 @@ gp_status gp_fit_batch(gp_ctx* ctx, int32_t count, const gp_params* params, cons
       hipEventRecord(ev_heads[f], fs[f]);
       hipStreamWaitEvent(cs, ev_heads[f], 0);
     }
-    // one persistent Gram launch for all mixed problems
-    if (!items.empty()) launch_gram_mixed_batch(probs_dev, items_dev, (int)items.size(), counter, lds, cs, nullptr);
+    // one persistent Gram launch per scheme for all mixed problems
+    if (nsch[0]) launch_gram_mixed_batch(probs_dev, items_dev, nsch[0], true, counter, lds[0], cs, nullptr);
+    if (nsch[1])
+      launch_gram_mixed_batch(probs_dev, items_dev + nsch[0], nsch[1], false, counter + 1, lds[1], cs, nullptr);
     hipEventRecord(ev_fork, cs);
     for (int f = 0; f < kForks; ++f) hipStreamWaitEvent(fs[f], ev_fork, 0);
     for (int k = 0; k < count; ++k) {
       gp_model* m = ms[k];
       hipStream_t fk = fs[k % kForks];
       const int M = (int)Ms[k];
-      if (params[k].precision == GP_PREC_MIXED) {
+      if (prec_mixed(params[k].precision)) {
         launch_gram_mixed_reduce((const float*)(ws + off[k] + Ls[k].gpart), Ls[k].g.splits_total, Ls[k].g.T, M,
                                  m->reg, true, m->A, fk);
       } else {

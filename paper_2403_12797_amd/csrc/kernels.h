@@ -33,25 +33,29 @@ int64_t gram_f64_part_elems(int64_t N, int M, int* splitk_out);
 void launch_gram_f64(const double* x, int64_t N, int p, int n, int M, const double* tab,
                      const double* reg, double* part, double* A, hipStream_t s, Prof* prof = nullptr);
 
-// a3 (mixed): split-BF16 MFMA Gram, FP32 accumulate, FP64 split-K reduce.
-// Samples are processed in chunks of `chunk` (a multiple of 16); each
-// (upper tile, chunk) writes an FP32 partial, at most ~4 GB of partials per
-// pass.  tab32 holds gram_mixed_table_elems() floats (1-D tables).
+// a3 (mixed): split MFMA Gram on scaled Phi (f16: two FP16 terms, three
+// products; else three BF16 terms, six products), FP32 accumulate, FP64
+// split-K reduce.  Samples are processed in chunks of `chunk` (a multiple of
+// 16); each (upper tile, chunk) writes an FP32 partial, at most 8 GiB of
+// partials per pass.  tab32 holds gram_mixed_table_elems() floats: the 1-D
+// tables and their per-row maxima, written by launch_gram_mixed_table(),
+// which must run before launch_gram_mixed() on the same stream.
 struct GramPlan {
   int T, ntiles, chunk, splits_total, splits_per_pass, passes;
 };
 GramPlan gram_mixed_plan(int64_t N, int M, int chunk /* <= 0: default */);
 int64_t gram_mixed_part_elems(const GramPlan& g);
 int64_t gram_mixed_table_elems(int64_t N, int p, int n);
-size_t gram_mixed_lds_bytes(int p, int n, int M);
+size_t gram_mixed_lds_bytes(int p, int n, int M, bool f16);
 void launch_gram_mixed_table(const double* x, int64_t N, int p, int n, const double* tab, float* tab32,
                              hipStream_t s);
-void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const GramPlan& g,
+void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const GramPlan& g, bool f16,
                        const double* tab, const double* reg, float* part, float* tab32, double* A,
                        hipStream_t s, Prof* prof = nullptr);
 void launch_gram_mixed_reduce(const float* part, int splits, int T, int M, const double* reg,
                               bool first, double* A, hipStream_t s);
-// Batched: one persistent launch over the work items of many problems.
+// Batched: one persistent launch over the work items of many problems that
+// share a Gram scheme.
 struct GramProb {
   const float* tab32;
   float* part;
@@ -61,7 +65,7 @@ struct GramProb {
 struct GramItem {
   int prob, tile, h, split;
 };
-void launch_gram_mixed_batch(const GramProb* probs_dev, const GramItem* items_dev, int nitems,
+void launch_gram_mixed_batch(const GramProb* probs_dev, const GramItem* items_dev, int nitems, bool f16,
                              int* counter, size_t lds, hipStream_t s, Prof* prof = nullptr);
 
 // a4: blocked Cholesky in place (lower), block inverses Dinv[M/64][64*64],

@@ -1,16 +1,23 @@
-// Mixed-precision kernels: fused Phi-generation + split-BF16 MFMA Gram (a3)
+// Mixed-precision kernels: fused Phi-generation + split-FP16 MFMA Gram (a3)
 // and the split-BF16 predictive variance with the fused FP64 mean (a5).
 //
-// Split-BF16 arithmetic.  A value v (first rounded once to FP32) is written
-// as v = hi + mid + lo with hi = bf16(v), mid = bf16(v - hi), lo = bf16(v -
-// hi - mid), every bf16() round-to-nearest-even; each subtraction is exact in
-// FP32, so the three terms carry the FP32 value.  A product a*b is taken as
-// the six MFMA products of relative order >= 2^-16:
-//   ah*bh + ah*bm + am*bh + ah*bl + al*bh + am*bm
-// with FP32 accumulation.  The variance contraction uses two terms (hi, lo)
-// and three products (ah*bh + ah*bl + al*bh).
+// Gram scaling.  Every 1-D table row (dimension j, order k) is scaled by a
+// power of two 2^e(j,k) that brings its largest magnitude over the samples
+// into [0.5, 1), the last dimension's rows by a further 2^15, so each scaled
+// Phi value lies below 2^15 (inside the FP16 range) and a column's scale is
+// 2^(sum of its rows' exponents); the finished tile is unscaled by the exact
+// power of two of its row and column.  Two Gram schemes, FP32 accumulation:
+//  * split-FP16: v = hi + lo with hi = f16(v), lo = f16(v - hi), both
+//    round-to-nearest-even (the subtraction is exact in FP32), about 22
+//    significant bits; a*b as the three products ah*bh + ah*bl + al*bh.
+//  * split-BF16: v = hi + mid + lo, each term bf16 of the remainder; a*b as
+//    the six products of relative order >= 2^-16:
+//    ah*bh + ah*bm + am*bh + ah*bl + al*bh + am*bm.
 //
-// MFMA v_mfma_f32_32x32x16_bf16 operand layout (lane l of a wave64):
+// Split-BF16 arithmetic (variance).  v = hi + lo with hi = bf16(v), lo =
+// bf16(v - hi); a product is taken as ah*bh + ah*bl + al*bh.
+//
+// MFMA v_mfma_f32_32x32x16_{f16,bf16} operand layout (lane l of a wave64):
 //   A (32 x 16): lane l holds A[l % 32][8*(l/32) .. 8*(l/32)+7]
 //   B (16 x 32): lane l holds B[8*(l/32) .. +7][l % 32]
 //   D (32 x 32): element r of the lane's float16 is
@@ -40,7 +47,7 @@ __device__ __forceinline__ uint32_t pack_bf16x2_opaque(float a, float b) {
 __device__ __forceinline__ float bf16lo_f(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16hi_f(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
-// Three-term split of a pair of FP32 values; returns packed (hi, mid, lo).
+// Three-term BF16 split of a pair of FP32 values; returns packed (hi, mid, lo).
 __device__ __forceinline__ void split3(float a, float b, uint32_t& h, uint32_t& m, uint32_t& l) {
   h = pack_bf16x2_opaque(a, b);
   const float ra = a - bf16lo_f(h), rb = b - bf16hi_f(h);
@@ -53,27 +60,98 @@ __device__ __forceinline__ void split2(float a, float b, uint32_t& h, uint32_t& 
   l = pack_bf16x2(a - bf16lo_f(h), b - bf16hi_f(h));
 }
 
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ f32x16 mfma_f16(const f16x8& a, const f16x8& b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+// Round-to-nearest-even FP32 -> FP16 of two values, packed (lo half = a).
+__device__ __forceinline__ uint32_t pack_f16x2(float a, float b) {
+  f16x2 v = {(_Float16)a, (_Float16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
+// Two-term FP16 split of a pair of FP32 values; returns packed (hi, lo).
+__device__ __forceinline__ void split2h(float a, float b, uint32_t& h, uint32_t& l) {
+  h = pack_f16x2(a, b);
+  asm volatile("" : "+v"(h));
+  const f16x2 hv = __builtin_bit_cast(f16x2, h);
+  l = pack_f16x2(a - (float)hv[0], b - (float)hv[1]);
+}
+
 // ================================================================ a3 mixed Gram
 // Pre-pass: the 1-D eigenfunctions of every sample, computed in FP64 and
 // stored as FP32 in stage-contiguous blocks of 16 samples:
-//   tab32[s][j*n + k][16]  (s = sample / 16), zero for samples >= N.
+//   tab32[s][j*n + k][16]  (s = sample / 16), zero for samples >= N,
+// followed by kGmMaxWords words: the largest |value| of each row j*n + k
+// over all samples (FP32 bits, which order like the magnitudes).
 constexpr int kGmKC = 16;
+constexpr int kGmMaxWords = GP_MAX_P * GP_MAX_N;
+constexpr int kGmTableBlocks = 1024;
 
-__global__ void phi1d_table_kernel(const double* __restrict__ x, int64_t N, int p, int n,
-                                   const double* __restrict__ tab, float* __restrict__ out, int64_t nstage) {
-  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (stage, dim, sample-in-stage)
-  if (u >= nstage * p * kGmKC) return;
-  const int i = (int)(u % kGmKC);
-  const int j = (int)((u / kGmKC) % p);
-  const int64_t st = u / ((int64_t)kGmKC * p);
-  const int64_t row = st * kGmKC + i;
-  float* o = out + (st * p * n + (int64_t)j * n) * kGmKC + i;
-  if (row < N) {
+// Grid-stride over (stage, dimension, sample-in-stage); the 16 lanes of one
+// (stage, dimension) are consecutive and reduce their maxima by shuffles,
+// the work-group through LDS, then one atomic per row and work-group.
+__global__ void __launch_bounds__(256) phi1d_table_kernel(const double* __restrict__ x, int64_t N, int p, int n,
+                                                          const double* __restrict__ tab, float* __restrict__ out,
+                                                          int64_t nstage, unsigned* __restrict__ tmax) {
+  __shared__ unsigned smax[kGmMaxWords];
+  for (int r = threadIdx.x; r < p * n; r += blockDim.x) smax[r] = 0u;
+  __syncthreads();
+  const int64_t total = nstage * p * kGmKC;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total; u += stride) {
+    const int i = (int)(u % kGmKC);
+    const int j = (int)((u / kGmKC) % p);
+    const int64_t st = u / ((int64_t)kGmKC * p);
+    const int64_t row = st * kGmKC + i;
+    float* o = out + (st * p * n + (int64_t)j * n) * kGmKC + i;
+    // phi_{k+1}(x) = sqrt(beta) exp(-delta^2 x^2) h_k(alpha beta x), h_k the
+    // normalised Hermite recurrence (eq. 15); zero past the last sample
     const double* dc = tab + kTabDim + j * kDimStride;
-    phi_1d<double, float>(x[row * p + j], dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, kGmKC);
-  } else {
-    for (int k = 0; k < n; ++k) o[k * kGmKC] = 0.0f;
+    const double* rc1 = tab + kTabRc1;
+    const double* rc2 = tab + kTabRc2;
+    const bool live = row < N;
+    const double xv = live ? x[row * p + j] : 0.0;
+    const double t = dc[0] * xv;
+    const double e = live ? dc[2] * exp(-dc[1] * xv * xv) : 0.0;
+    double h0 = 1.0, h1 = 1.4142135623730951 * t;
+    for (int k = 0; k < n; ++k) {
+      double hk;
+      if (k == 0) {
+        hk = 1.0;
+      } else if (k == 1) {
+        hk = h1;
+      } else {
+        hk = rc1[k - 1] * t * h1 - rc2[k - 1] * h0;
+        h0 = h1;
+        h1 = hk;
+      }
+      const float v = (float)(e * hk);
+      o[k * kGmKC] = v;
+      unsigned m = __float_as_uint(fabsf(v));
+#pragma unroll
+      for (int off = 1; off < kGmKC; off <<= 1) m = max(m, (unsigned)__shfl_xor((int)m, off, kGmKC));
+      if (i == 0 && m) atomicMax(&smax[j * n + k], m);
+    }
   }
+  __syncthreads();
+  for (int r = threadIdx.x; r < p * n; r += blockDim.x)
+    if (smax[r]) atomicMax(&tmax[r], smax[r]);
+}
+
+// Exponent e(j,k) of a row's scale from its largest magnitude (zero rows:
+// 0), the last dimension's rows raised by 15; bounded so that 2^e stays a
+// normal FP32 number.
+constexpr int kGmF16Top = 15;
+__device__ __forceinline__ int gm_row_exp(unsigned maxbits, bool last) {
+  int e = 0;
+  if (maxbits) {
+    int E;
+    frexpf(__uint_as_float(maxbits), &E);
+    e = -E;
+  }
+  e += last ? kGmF16Top : 0;
+  return min(max(e, -120), 100);
 }
 
 // Gram work-group: rows I*256..+256 and columns J*256 + h*128..+128 (half h
@@ -100,11 +178,12 @@ constexpr int kG2H = 128;                                   // columns per work-
 constexpr int kG2Threads = 512;
 constexpr int kG2Flush = 16;                                // stages per MFMA chain
 constexpr int kG2Slots = kGmT + kG2H;                       // 384 column slots per stage
-constexpr int kG2SlotPitch = kGmKC + 8;                     // bf16 per slot (16 samples + pad)
+constexpr int kG2SlotPitch = kGmKC + 8;                     // f16 per slot (16 samples + pad)
 constexpr int kG2TabPitch = kGmKC + 4;                      // floats per table / prefix row (16 + pad)
 constexpr int kGmChunk = 8192;                              // samples per FP32 partial
 constexpr int64_t kGmPartCap = 8ll << 30;                   // bytes of partials per pass
-constexpr int kGmStageElems = 3 * kG2Slots * kG2SlotPitch;  // bf16 per stage buffer
+// 16-bit elements per stage buffer: [term][slot][sample]
+__host__ __device__ constexpr int gm_stage_elems(bool f16) { return (f16 ? 2 : 3) * kG2Slots * kG2SlotPitch; }
 
 GramPlan gram_mixed_plan(int64_t N, int M, int chunk) {
   GramPlan g;
@@ -131,56 +210,69 @@ int64_t gram_mixed_part_elems(const GramPlan& g) { return (int64_t)g.splits_per_
 // Zero stages past the end let the kernel prefetch without bounds tests: a
 // work-group reads at most four stages past its last one.
 constexpr int kGmTabPad = 4;
-int64_t gram_mixed_table_elems(int64_t N, int p, int n) { return (ceil_div(N, kGmKC) + kGmTabPad) * p * n * kGmKC; }
+__host__ __device__ inline int64_t gm_max_offset(int64_t N, int p, int n) {
+  return (ceil_div(N, kGmKC) + kGmTabPad) * p * n * kGmKC;
+}
+int64_t gram_mixed_table_elems(int64_t N, int p, int n) { return gm_max_offset(N, p, n) + kGmMaxWords; }
 
 // Prefix rows per stage: I-block prefixes then J-half prefixes (L consecutive
 // columns hold at most L/n + 2 distinct prefixes).
 __host__ __device__ inline int gm_pre_rows_i(int n, int M) { return min(kGmT, M) / n + 2; }
 __host__ __device__ inline int gm_pre_rows(int n, int M) { return gm_pre_rows_i(n, M) + min(kG2H, M) / n + 2; }
 
-static size_t gram_lds_bytes(int p, int n, int M) {
-  return 2 * (size_t)kGmStageElems * sizeof(__bf16) + 3 * (size_t)p * n * kG2TabPitch * sizeof(float) +
-         2 * (size_t)gm_pre_rows(n, M) * kG2TabPitch * sizeof(float) +
+static size_t gram_lds_bytes(int p, int n, int M, bool f16) {
+  return 2 * (size_t)gm_stage_elems(f16) * 2 + 3 * (size_t)p * n * kG2TabPitch * sizeof(float) +
+         2 * (size_t)gm_pre_rows(n, M) * kG2TabPitch * sizeof(float) + kG2Slots * sizeof(int) +
          (size_t)gm_pre_rows(n, M) * GP_MAX_P * sizeof(uint16_t) + 16;
 }
 
-// Split NS values into three BF16 terms and store them at [term][slot][s_off..].
-template <int NS>
-__device__ __forceinline__ void gm_store3(const float* v, __bf16* __restrict__ stage, int slot, int s_off) {
-  uint32_t h[NS / 2], m[NS / 2], l[NS / 2];
+// Split NS values into the scheme's terms and store them at [term][slot][s_off..].
+template <bool F16, int NS, typename E>
+__device__ __forceinline__ void gm_store(const float* v, E* __restrict__ stage, int slot, int s_off) {
+  constexpr int NT = F16 ? 2 : 3;
+  uint32_t w[NT][NS / 2];
 #pragma unroll
-  for (int q = 0; q < NS / 2; ++q) split3(v[2 * q], v[2 * q + 1], h[q], m[q], l[q]);
-  __bf16* dh = stage + (0 * kG2Slots + slot) * kG2SlotPitch + s_off;
-  __bf16* dm = stage + (1 * kG2Slots + slot) * kG2SlotPitch + s_off;
-  __bf16* dl = stage + (2 * kG2Slots + slot) * kG2SlotPitch + s_off;
-  if constexpr (NS == 8) {
-    *reinterpret_cast<uint4*>(dh) = uint4{h[0], h[1], h[2], h[3]};
-    *reinterpret_cast<uint4*>(dm) = uint4{m[0], m[1], m[2], m[3]};
-    *reinterpret_cast<uint4*>(dl) = uint4{l[0], l[1], l[2], l[3]};
-  } else {
-    *reinterpret_cast<uint2*>(dh) = uint2{h[0], h[1]};
-    *reinterpret_cast<uint2*>(dm) = uint2{m[0], m[1]};
-    *reinterpret_cast<uint2*>(dl) = uint2{l[0], l[1]};
+  for (int q = 0; q < NS / 2; ++q) {
+    if constexpr (F16)
+      split2h(v[2 * q], v[2 * q + 1], w[0][q], w[1][q]);
+    else
+      split3(v[2 * q], v[2 * q + 1], w[0][q], w[1][q], w[2][q]);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    E* d = stage + (t * kG2Slots + slot) * kG2SlotPitch + s_off;
+    if constexpr (NS == 8)
+      *reinterpret_cast<uint4*>(d) = uint4{w[t][0], w[t][1], w[t][2], w[t][3]};
+    else
+      *reinterpret_cast<uint2*>(d) = uint2{w[t][0], w[t][1]};
   }
 }
 
 // One work item: tile `tile` (upper-triangle index), half h, samples
 // [r0, r0 + chunk) of a problem; writes the item's FP32 partial 256x256 tile
 // (half h) at `out`.
+template <bool F16>
 __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __restrict__ tab32, int64_t N, int P,
                                           int n, int M, int T, int tile, int h, int64_t r0, int chunk,
                                           float* __restrict__ out) {
   // LDS: two stage buffers of split Phi, three 1-D table buffers, two prefix
   // buffers.  Addressed as base + offset so the compiler keeps them in LDS.
-  __bf16* const stg0 = reinterpret_cast<__bf16*>(smraw);
-  float* const tb0 = reinterpret_cast<float*>(smraw + 2 * kGmStageElems * sizeof(__bf16));
+  using E = std::conditional_t<F16, _Float16, __bf16>;
+  using V8 = std::conditional_t<F16, f16x8, bf16x8>;
+  constexpr int NT = F16 ? 2 : 3;                 // terms per value
+  constexpr int SE = gm_stage_elems(F16);
+  E* const stg0 = reinterpret_cast<E*>(smraw);
+  float* const tb0 = reinterpret_cast<float*>(smraw + 2 * SE * sizeof(E));
   const int rows = P * n;                       // 1-D table rows per stage
   const int tbs = rows * kG2TabPitch;           // floats per table buffer
   float* const pr0 = tb0 + 3 * tbs;
   const int prs = gm_pre_rows(n, M) * kG2TabPitch; // floats per prefix buffer
+  // per column slot: the exponent of its scale (sum over its table rows)
+  int* const csc = reinterpret_cast<int*>(pr0 + 2 * prs);
   // per prefix row: the 1-D table rows of its leading digits; entry
   // GP_MAX_P-1 flags a row with no prefix (value 1 kept out of the sums)
-  uint16_t* const pre_off = reinterpret_cast<uint16_t*>(pr0 + 2 * prs);
+  uint16_t* const pre_off = reinterpret_cast<uint16_t*>(csc + kG2Slots);
+  const unsigned* const tmax = reinterpret_cast<const unsigned*>(tab32 + gm_max_offset(N, P, n));
   const int tchunks = rows * (kGmKC / 4);       // float4 per stage of the table
 
   int I = 0;
@@ -234,14 +326,18 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   // 1-D tables of one stage: at most 128 rows x 16 floats = 512 float4, one per thread
   // (requested two stages before they are stored, alternating between two
   // registers, so the global latency is hidden behind two stages of work)
+  // (each thread stores one table row's 4 samples, scaled by the row's 2^e)
   float4 treg0, treg1;
+  const int trow = tid / (kGmKC / 4);
+  const float tsc = tid < tchunks ? ldexpf(1.0f, gm_row_exp(tmax[trow], trow >= (P - 1) * n)) : 0.0f;
   auto load_tab = [&](int64_t gst, float4& r) {
     if (tid < tchunks) r = reinterpret_cast<const float4*>(tab32 + gst * rows * kGmKC)[tid];
   };
   auto store_tab = [&](float* dst, const float4& r) {
     if (tid < tchunks) {
-      const int row = tid / (kGmKC / 4), c4 = tid % (kGmKC / 4);
-      *reinterpret_cast<float4*>(dst + row * kG2TabPitch + c4 * 4) = r;
+      const int c4 = tid % (kGmKC / 4);
+      *reinterpret_cast<float4*>(dst + trow * kG2TabPitch + c4 * 4) =
+          float4{r.x * tsc, r.y * tsc, r.z * tsc, r.w * tsc};
     }
   };
   // prefix rows of one stage from its 1-D tables: one (row, 4 samples) per
@@ -280,7 +376,7 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
     g.pj = *reinterpret_cast<const float4*>(Pr + preJ);
     g.lj = *reinterpret_cast<const float4*>(Tb + lastJ);
   };
-  auto gen_store = [&](const GenIn& g, __bf16* D) {
+  auto gen_store = [&](const GenIn& g, E* D) {
     {
       float v[8];
 #pragma unroll
@@ -294,7 +390,7 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = 0.0f;
       }
-      gm_store3<8>(v, D, tid & 255, sI);
+      gm_store<F16, 8>(v, D, tid & 255, sI);
     }
     {
       // J half (on diagonal tiles these slots are unused and get zeros)
@@ -304,10 +400,10 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
       v[2] = g.pj.z * g.lj.z;
       v[3] = g.pj.w * g.lj.w;
       if (!validJ) v[0] = v[1] = v[2] = v[3] = 0.0f;
-      gm_store3<4>(v, D, kGmT + (tid & 127), sJ);
+      gm_store<F16, 4>(v, D, kGmT + (tid & 127), sJ);
     }
   };
-  auto generate = [&](const float* Tb, const float* Pr, __bf16* D) {
+  auto generate = [&](const float* Tb, const float* Pr, E* D) {
     GenIn g;
     gen_read(Tb, Pr, g);
     gen_store(g, D);
@@ -324,6 +420,18 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
       rem /= n;
     }
     po[GP_MAX_P - 1] = hi < 0 ? 1 : 0;
+  }
+  for (int sl = tid; sl < kG2Slots; sl += kG2Threads) {
+    const int c = sl < kGmT ? cI0 + sl : cJ0 + sl - kGmT;
+    int e = 0;
+    if (c < M && (sl < kGmT || genJ)) {
+      int rem = c;
+      for (int j = P - 1; j >= 0; --j) {
+        e += gm_row_exp(tmax[j * n + rem % n], j == P - 1);
+        rem /= n;
+      }
+    }
+    csc[sl] = e;
   }
   // (pre_off is read after the prologue's first barrier)
   // prologue: tables of stages 0..2, prefixes of stages 0..1, Phi of stage 0
@@ -349,46 +457,44 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
     // inputs of stage st+1 (past the chunk end they produce unused values)
     GenIn gin;
     gen_read(tb0 + ((st + 1) % 3) * tbs, pr0 + ((st + 1) & 1) * prs, gin);
-    const __bf16* S = stg0 + (st & 1) * kGmStageElems;
-    bf16x8 aop[2][3], bop[2][3];
+    const E* S = stg0 + (st & 1) * SE;
+    V8 aop[2][NT], bop[2][NT];
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        bop[cb][q] = *reinterpret_cast<const bf16x8*>(
+      for (int q = 0; q < NT; ++q)
+        bop[cb][q] = *reinterpret_cast<const V8*>(
             S + (q * kG2Slots + jslot + wc * 64 + cb * 32 + (lane & 31)) * kG2SlotPitch + (lane >> 5) * 8);
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        aop[rb][q] = *reinterpret_cast<const bf16x8*>(
+      for (int q = 0; q < NT; ++q)
+        aop[rb][q] = *reinterpret_cast<const V8*>(
             S + (q * kG2Slots + wr * 64 + rb * 32 + (lane & 31)) * kG2SlotPitch + (lane >> 5) * 8);
-    // six products, interleaved over the four accumulators
+    // the scheme's products (smallest first), interleaved over the four accumulators
+    auto prod = [&](int qa, int qb) {
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][1], bop[cb][1], acc[rb][cb]);  // mid*mid
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][2], bop[cb][0], acc[rb][cb]);  // lo*hi
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][2], acc[rb][cb]);  // hi*lo
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][1], bop[cb][0], acc[rb][cb]);  // mid*hi
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][1], acc[rb][cb]);  // hi*mid
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_bf16(aop[rb][0], bop[cb][0], acc[rb][cb]);  // hi*hi
-    gen_store(gin, stg0 + ((st + 1) & 1) * kGmStageElems);
+        for (int cb = 0; cb < 2; ++cb) {
+          if constexpr (F16)
+            acc[rb][cb] = mfma_f16(aop[rb][qa], bop[cb][qb], acc[rb][cb]);
+          else
+            acc[rb][cb] = mfma_bf16(aop[rb][qa], bop[cb][qb], acc[rb][cb]);
+        }
+    };
+    if constexpr (!F16) {
+      prod(1, 1);   // mid*mid
+      prod(2, 0);   // lo*hi
+      prod(0, 2);   // hi*lo
+      prod(1, 0);   // mid*hi
+      prod(0, 1);   // hi*mid
+    } else {
+      prod(1, 0);   // lo*hi
+      prod(0, 1);   // hi*lo
+    }
+    prod(0, 0);     // hi*hi
+    gen_store(gin, stg0 + ((st + 1) & 1) * SE);
     make_pre(tb0 + ((st + 2) % 3) * tbs, pr0 + (st & 1) * prs);
     store_tab(tb0 + (st % 3) * tbs, Rstore);
     __syncthreads();
@@ -419,13 +525,15 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
       for (int r = 0; r < 16; ++r) {
         const int row = wr * 64 + rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int cl = h * kG2H + wc * 64 + cb * 32 + (lane & 31);
-        out[row * kGmT + cl] = sum[rb][cb][r];
+        const int cs = jslot + wc * 64 + cb * 32 + (lane & 31);   // the column's slot
+        out[row * kGmT + cl] = ldexpf(sum[rb][cb][r], -(csc[row] + csc[cs]));
       }
 }
 
 // A (+)= sum of the pass's FP32 partials in split order (FP64); the first pass
 // also adds reg on the diagonal.  Writes both triangles.
 // Single problem: grid (2 * ntiles, splits of this pass).
+template <bool F16>
 __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __restrict__ tab32, int64_t N, int p,
                                                                 int n, int M, int T, int split0, int chunk,
                                                                 float* __restrict__ part) {
@@ -433,11 +541,12 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_kernel(const float* __r
   const int ntiles = T * (T + 1) / 2;
   const int tile = blockIdx.x >> 1;
   float* out = part + ((int64_t)blockIdx.y * ntiles + tile) * (kGmT * kGmT);
-  gram_item(smraw, tab32, N, p, n, M, T, tile, blockIdx.x & 1, (int64_t)(split0 + blockIdx.y) * chunk, chunk, out);
+  gram_item<F16>(smraw, tab32, N, p, n, M, T, tile, blockIdx.x & 1, (int64_t)(split0 + blockIdx.y) * chunk, chunk, out);
 }
 
 // Many problems in one persistent launch: work-groups take items from a
 // longest-first list through an atomic counter until it runs out.
+template <bool F16>
 __global__ void __launch_bounds__(kG2Threads) gram_mixed_batch_kernel(const GramProb* __restrict__ probs,
                                                                       const GramItem* __restrict__ items, int nitems,
                                                                       int* __restrict__ counter) {
@@ -453,7 +562,7 @@ __global__ void __launch_bounds__(kG2Threads) gram_mixed_batch_kernel(const Gram
     const GramProb pr = probs[wi.prob];
     const int ntiles = pr.T * (pr.T + 1) / 2;
     float* out = pr.part + ((int64_t)wi.split * ntiles + wi.tile) * (kGmT * kGmT);
-    gram_item(smraw, pr.tab32, pr.N, pr.p, pr.n, pr.M, pr.T, wi.tile, wi.h, (int64_t)wi.split * pr.chunk, pr.chunk,
+    gram_item<F16>(smraw, pr.tab32, pr.N, pr.p, pr.n, pr.M, pr.T, wi.tile, wi.h, (int64_t)wi.split * pr.chunk, pr.chunk,
               out);
   }
 }
@@ -509,24 +618,27 @@ __global__ void __launch_bounds__(256) gram_mixed_reduce_kernel(const float* __r
   }
 }
 
-size_t gram_mixed_lds_bytes(int p, int n, int M) { return gram_lds_bytes(p, n, M); }
+size_t gram_mixed_lds_bytes(int p, int n, int M, bool f16) { return gram_lds_bytes(p, n, M, f16); }
 
 void launch_gram_mixed_table(const double* x, int64_t N, int p, int n, const double* tab, float* tab32,
                              hipStream_t s) {
   const int64_t nstage = ceil_div(N, kGmKC) + kGmTabPad;
-  hipLaunchKernelGGL(phi1d_table_kernel, dim3(ceil_div(nstage * p * kGmKC, 256)), dim3(256), 0, s, x, N, p, n, tab,
-                     tab32, nstage);
+  unsigned* tmax = reinterpret_cast<unsigned*>(tab32 + gm_max_offset(N, p, n));
+  launch_fill_zero_int(reinterpret_cast<int*>(tmax), p * n, s);
+  const int blocks = (int)std::min<int64_t>(kGmTableBlocks, ceil_div(nstage * p * kGmKC, 256));
+  hipLaunchKernelGGL(phi1d_table_kernel, dim3(blocks), dim3(256), 0, s, x, N, p, n, tab, tab32, nstage, tmax);
 }
 
-void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const GramPlan& g, const double* tab,
-                       const double* reg, float* part, float* tab32, double* A, hipStream_t s, Prof* prof) {
-  launch_gram_mixed_table(x, N, p, n, tab, tab32, s);
+void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const GramPlan& g, bool f16,
+                       const double* tab, const double* reg, float* part, float* tab32, double* A, hipStream_t s,
+                       Prof* prof) {
   for (int ps = 0; ps < g.passes; ++ps) {
     const int split0 = ps * g.splits_per_pass;
     const int cnt = std::min(g.splits_per_pass, g.splits_total - split0);
     prof_mark(prof, GP_PH_GRAM, true, s);
-    hipLaunchKernelGGL(gram_mixed_kernel, dim3(2 * g.ntiles, cnt), dim3(kG2Threads), gram_lds_bytes(p, n, M), s, tab32,
-                       N, p, n, M, g.T, split0, g.chunk, part);
+    hipLaunchKernelGGL(f16 ? gram_mixed_kernel<true> : gram_mixed_kernel<false>, dim3(2 * g.ntiles, cnt),
+                       dim3(kG2Threads), gram_lds_bytes(p, n, M, f16), s, tab32, N, p, n, M, g.T, split0, g.chunk,
+                       part);
     prof_mark(prof, GP_PH_GRAM, false, s);
     prof_mark(prof, GP_PH_GRAM_REDUCE, true, s);
     launch_gram_mixed_reduce(part, cnt, g.T, M, reg, ps == 0, A, s);
@@ -541,15 +653,15 @@ void launch_gram_mixed_reduce(const float* part, int splits, int T, int M, const
                      first ? 1 : 0, A);
 }
 
-void launch_gram_mixed_batch(const GramProb* probs_dev, const GramItem* items_dev, int nitems, int* counter,
-                             size_t lds, hipStream_t s, Prof* prof) {
+void launch_gram_mixed_batch(const GramProb* probs_dev, const GramItem* items_dev, int nitems, bool f16,
+                             int* counter, size_t lds, hipStream_t s, Prof* prof) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const int grid = std::max(1, std::min(nitems, cus));
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
   prof_mark(prof, GP_PH_GRAM, true, s);
-  hipLaunchKernelGGL(gram_mixed_batch_kernel, dim3(grid), dim3(kG2Threads), lds, s, probs_dev, items_dev, nitems,
-                     counter);
+  hipLaunchKernelGGL(f16 ? gram_mixed_batch_kernel<true> : gram_mixed_batch_kernel<false>, dim3(grid),
+                     dim3(kG2Threads), lds, s, probs_dev, items_dev, nitems, counter);
   prof_mark(prof, GP_PH_GRAM, false, s);
 }
 
@@ -987,10 +1099,11 @@ hipError_t configure_kernels() {
   // dynamic LDS limit: 160 KB per work-group minus room for small static arrays
   const int big = kMaxDynLds;
   hipError_t e = hipSuccess;
-  e = hipFuncSetAttribute((const void*)gram_mixed_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)gram_mixed_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  if (e != hipSuccess) return e;
+  for (const void* k : {(const void*)gram_mixed_kernel<true>, (const void*)gram_mixed_kernel<false>,
+                        (const void*)gram_mixed_batch_kernel<true>, (const void*)gram_mixed_batch_kernel<false>}) {
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+  }
   for (int p = 1; p <= GP_MAX_P; ++p)
     for (int tn : {128, 256}) {
       e = hipFuncSetAttribute((const void*)predict_kernel_for(tn, p), hipFuncAttributeMaxDynamicSharedMemorySize, big);

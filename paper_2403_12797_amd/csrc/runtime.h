@@ -13,6 +13,9 @@
 
 #include "common.h"
 
+// Both mixed modes share everything but the Gram scheme.
+inline bool prec_mixed(int precision) { return precision == GP_PREC_MIXED || precision == GP_PREC_MIXED_F16; }
+
 struct gp_model {
   gp_ctx* ctx = nullptr;
   int p = 0, n = 0;

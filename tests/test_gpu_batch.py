@@ -49,21 +49,26 @@ def single(ctx, torch, P, prec):
     return w, mean.cpu().numpy(), var.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", [B.PREC_MIXED, B.PREC_FP64])
+@pytest.mark.parametrize("prec", [B.PREC_MIXED, B.PREC_MIXED_F16, B.PREC_FP64, "all three"])
 def test_batch_equals_single_and_oracle(torch_cuda, prec):
+    """Every problem of a batch equals its single fit bitwise; "all three"
+    mixes FP16-Gram, BF16-Gram and FP64 problems in one batch (one persistent
+    Gram launch per split scheme)."""
     torch = torch_cuda
     Ps = batch_problems()
+    modes = (B.PREC_MIXED_F16, B.PREC_MIXED, B.PREC_FP64)
+    precs = [modes[k % 3] for k in range(len(Ps))] if prec == "all three" else [prec] * len(Ps)
     with B.Context(0) as ctx:
         dx = [(dev(torch, P.x), dev(torch, P.y), P.p, P.n, P.sigma, P.eps, P.alpha) for P in Ps]
-        models = ctx.fit_batch(dx, precision=prec)
+        models = ctx.fit_batch(dx, precision=precs)
         xs = [dev(torch, P.xs) for P in Ps]
         means = [torch.empty(P.Ns, dtype=torch.float64, device="cuda") for P in Ps]
         vars_ = [torch.empty(P.Ns, dtype=torch.float64, device="cuda") for P in Ps]
         ctx.predict_batch(models, xs, means, vars_)
         torch.cuda.synchronize()
         for k, P in enumerate(Ps):
-            print(f"[case] batch {P.name} prec={prec} M={P.M}", flush=True)
-            w_s, m_s, v_s = single(ctx, torch, P, prec)
+            print(f"[case] batch {P.name} prec={precs[k]} M={P.M}", flush=True)
+            w_s, m_s, v_s = single(ctx, torch, P, precs[k])
             assert np.array_equal(models[k].get(B.MODEL_W), w_s)
             assert np.array_equal(means[k].cpu().numpy(), m_s)
             assert np.array_equal(vars_[k].cpu().numpy(), v_s)
@@ -72,8 +77,8 @@ def test_batch_equals_single_and_oracle(torch_cuda, prec):
             f = o.fit(P.x, P.y, P.sigma, P.eps, P.alpha, P.n)
             om, ov = o.predict(f, P.xs)
             em, ev = rel(means[k].cpu().numpy(), om), rel(vars_[k].cpu().numpy(), ov)
-            print(f"[err] batch {P.name} prec={prec} mean={em:.3e} var={ev:.3e}", flush=True)
-            if prec == B.PREC_MIXED:
+            print(f"[err] batch {P.name} prec={precs[k]} mean={em:.3e} var={ev:.3e}", flush=True)
+            if precs[k] != B.PREC_FP64:
                 assert em <= 1e-5 and ev <= 1e-4
             else:
                 assert em <= 1e-10 and ev <= 1e-10
@@ -108,7 +113,7 @@ def test_autotune_then_fit(torch_cuda):
         chunk = ctx.autotune(P.p, P.n, P.N)
         print(f"[case] autotune p=3 n=8 N=40000 -> chunk {chunk}", flush=True)
         assert chunk % 16 == 0 and 1024 <= chunk <= 32768
-        w, mean, var = single(ctx, torch, P, B.PREC_MIXED)
+        w, mean, var = single(ctx, torch, P, B.PREC_MIXED_F16)
     f = o.fit(P.x, P.y, P.sigma, P.eps, P.alpha, P.n)
     om, ov = o.predict(f, P.xs)
     assert rel(mean, om) <= 1e-5 and rel(var, ov) <= 1e-4

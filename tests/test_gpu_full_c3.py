@@ -4,8 +4,8 @@ and the prediction of all 1e6 test points, checked at 2000 seeded test points
 against the FP64 oracle's values stored in tests/golden/c3_oracle.npz (written
 by tests/golden/make_c3_golden.py, which calls only the oracle).
 
-Tolerances (normwise relative over the sample): mixed 1e-5 mean / 1e-4
-variance; FP64 1e-10.
+Tolerances (normwise relative over the sample): both mixed modes 1e-5 mean /
+1e-4 variance; FP64 1e-10.
 """
 import os
 
@@ -36,7 +36,8 @@ def setup():
     ctx.close()
 
 
-@pytest.mark.parametrize("precision,tm,tv,tw", [(B.PREC_MIXED, 1e-5, 1e-4, None), (B.PREC_FP64, 1e-10, 1e-10, 1e-10)])
+@pytest.mark.parametrize("precision,tm,tv,tw", [(B.PREC_MIXED_F16, 1e-5, 1e-4, None), (B.PREC_MIXED, 1e-5, 1e-4, None),
+                                                (B.PREC_FP64, 1e-10, 1e-10, 1e-10)])
 def test_c3_full_size(setup, precision, tm, tv, tw):
     torch, P, (x, y, xs), g, ctx = setup
     print(f"[case] c3 full N={P.N} Ns={P.Ns} precision={precision}", flush=True)
@@ -60,7 +61,8 @@ def test_c3_full_size(setup, precision, tm, tv, tw):
     m.free()
 
 
-@pytest.mark.parametrize("precision,tm,tv", [(B.PREC_MIXED, 1e-5, 1e-4), (B.PREC_FP64, 1e-10, 1e-10)])
+@pytest.mark.parametrize("precision,tm,tv", [(B.PREC_MIXED_F16, 1e-5, 1e-4), (B.PREC_MIXED, 1e-5, 1e-4),
+                                             (B.PREC_FP64, 1e-10, 1e-10)])
 def test_c2_full_size(precision, tm, tv):
     """The whole c2 workload (p = 3, n = 8, M = 512, N = N_* = 1e5) against the
     oracle computed live (a few seconds of CPU)."""

@@ -3,7 +3,8 @@ on the same seeded inputs.
 
 Tolerances (normwise relative, ||got - want||_2 / ||want||_2 per result vector):
   FP64 path: 1e-10 on mean, variance and w.
-  Mixed path (split-BF16 Gram/predict, FP64 factorisation, one FP64
+  Mixed paths (Gram as split-BF16 with three terms or as scaled split-FP16
+  with two terms; split-BF16 variance; FP64 factorisation, one FP64
   refinement step): 1e-5 on the mean, 1e-4 on the variance.
 """
 import sys
@@ -77,7 +78,7 @@ def check(P, got, want, precision, extra=""):
     return e_mean, e_var
 
 
-@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED])
+@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED, B.PREC_MIXED_F16])
 def test_c1_full(torch_cuda, ctx, precision):
     P = wl.config("c1")
     got = gpu_fit_predict(torch_cuda, ctx, P, precision)
@@ -135,7 +136,7 @@ def test_factor_stages_multiblock(torch_cuda, ctx, seed, p, n, N):
     (11, 7, 3, 3000, 300),    # M = 2187: prediction reads prefix digits from global memory
     (12, 2, 64, 4000, 300),   # M = 4096, 128 table rows: 128-point prediction tiles
 ])
-@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED])
+@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED, B.PREC_MIXED_F16])
 def test_random_shapes(torch_cuda, ctx, seed, p, n, N, Ns, precision):
     P = wl.random_problem(seed, p, n, N, Ns)
     got = gpu_fit_predict(torch_cuda, ctx, P, precision)
@@ -143,7 +144,7 @@ def test_random_shapes(torch_cuda, ctx, seed, p, n, N, Ns, precision):
     check(P, got, want, precision)
 
 
-@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED])
+@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED, B.PREC_MIXED_F16])
 def test_c2_shape(torch_cuda, ctx, precision):
     """p = 3, n = 8 (M = 512), x ~ N(0, I): N reduced to 20000 for the oracle."""
     P = wl.config("c2", N=20_000, Ns=4_000)
@@ -151,7 +152,7 @@ def test_c2_shape(torch_cuda, ctx, precision):
     check(P, got, oracle_fit_predict(P), precision)
 
 
-@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED])
+@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED, B.PREC_MIXED_F16])
 def test_c3_shape_reduced(torch_cuda, ctx, precision):
     """p = 4, n = 8 (M = 4096), alpha = 1.2: N reduced to 30000 for the oracle."""
     P = wl.config("c3", N=30_000, Ns=3_000)
@@ -202,9 +203,36 @@ def test_invalid_arguments(torch_cuda, ctx):
         ctx.fit(x, yn, p=2, n=3, sigma=0.1, eps=1.0, alpha=1.0)
 
 
-def test_deterministic_repeat(torch_cuda, ctx):
+@pytest.mark.parametrize("precision", [B.PREC_MIXED, B.PREC_MIXED_F16])
+def test_deterministic_repeat(torch_cuda, ctx, precision):
     """Same inputs twice give bitwise-equal results (fixed reduction orders)."""
     P = wl.random_problem(12, 3, 6, 20000, 2000)
-    a = gpu_fit_predict(torch_cuda, ctx, P, B.PREC_MIXED)
-    b = gpu_fit_predict(torch_cuda, ctx, P, B.PREC_MIXED)
+    a = gpu_fit_predict(torch_cuda, ctx, P, precision)
+    b = gpu_fit_predict(torch_cuda, ctx, P, precision)
     assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("precision", [B.PREC_MIXED, B.PREC_MIXED_F16])
+@pytest.mark.parametrize("seed,p,n,spread,shift,eps,alpha", [
+    (31, 3, 8, 3.0, 2.0, None, None),   # wide inputs: |Phi| up to ~2e3
+    (33, 4, 6, 2.0, -3.0, None, None),  # shifted, one-sided
+    (37, 2, 16, 1.5, 1.0, 2.0, 1.0),    # long 1-D expansions, |Phi| up to ~7e2
+    (39, 4, 6, 2.5, 0.0, 1.0, 1.5),     # |Phi| up to ~8e4: beyond FP16 without the scaling
+])
+def test_mixed_gram_range(torch_cuda, ctx, precision, seed, p, n, spread, shift, eps, alpha):
+    """The Gram of both mixed schemes against the oracle's A (normwise 1e-6)
+    and the end results within the mixed tolerances, on inputs whose 1-D
+    eigenfunction values span many orders of magnitude (the FP16 scheme's
+    per-row power-of-two scaling has to keep them in range)."""
+    Q = wl.random_problem(seed, p, n, 6000, 500, dist="normal", eps=eps, alpha=alpha)
+    x = Q.x * spread
+    x[:, 0] += shift
+    xs = Q.xs * spread
+    xs[:, 0] += shift
+    y = np.cos(x).sum(axis=1) + np.random.default_rng(seed).normal(0.0, Q.sigma, size=x.shape[0])
+    P = wl.Problem(f"range{seed}_p{p}_n{n}", p, n, Q.sigma, Q.eps, Q.alpha, x, y, xs)
+    got = gpu_fit_predict(torch_cuda, ctx, P, precision)
+    want = oracle_fit_predict(P)
+    e_A = rel(got[0].get(B.MODEL_A), want[0].A)
+    check(P, got, want, precision, extra=f"A={e_A:.3e}")
+    assert e_A <= 1e-6

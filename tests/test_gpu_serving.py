@@ -53,7 +53,7 @@ def sync_result(ctx, torch, P, prec):
     return mean.cpu().numpy(), var.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", [B.PREC_MIXED, B.PREC_FP64])
+@pytest.mark.parametrize("prec", [B.PREC_MIXED, B.PREC_MIXED_F16, B.PREC_FP64])
 def test_alone_equals_mix_equals_sync(torch_cuda, prec):
     torch = torch_cuda
     Ps = problems()
