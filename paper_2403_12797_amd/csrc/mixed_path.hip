@@ -222,7 +222,7 @@ __host__ __device__ inline int gm_pre_rows(int n, int M) { return gm_pre_rows_i(
 
 static size_t gram_lds_bytes(int p, int n, int M, bool f16) {
   return 2 * (size_t)gm_stage_elems(f16) * 2 + 3 * (size_t)p * n * kG2TabPitch * sizeof(float) +
-         2 * (size_t)gm_pre_rows(n, M) * kG2TabPitch * sizeof(float) + kG2Slots * sizeof(int) +
+         2 * (size_t)(gm_pre_rows(n, M) + 1) * kG2TabPitch * sizeof(float) + kG2Slots * sizeof(int) +
          (size_t)gm_pre_rows(n, M) * GP_MAX_P * sizeof(uint16_t) + 16;
 }
 
@@ -266,11 +266,14 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   const int rows = P * n;                       // 1-D table rows per stage
   const int tbs = rows * kG2TabPitch;           // floats per table buffer
   float* const pr0 = tb0 + 3 * tbs;
-  const int prs = gm_pre_rows(n, M) * kG2TabPitch; // floats per prefix buffer
+  // prefix buffers: gm_pre_rows prefix rows, then a zero row that invalid
+  // columns use as their prefix, so they generate zeros
+  const int zrow = gm_pre_rows(n, M);
+  const int prs = (zrow + 1) * kG2TabPitch;     // floats per prefix buffer
   // per column slot: the exponent of its scale (sum over its table rows)
   int* const csc = reinterpret_cast<int*>(pr0 + 2 * prs);
-  // per prefix row: the 1-D table rows of its leading digits; entry
-  // GP_MAX_P-1 flags a row with no prefix (value 1 kept out of the sums)
+  // per prefix row: the 1-D table rows of its leading digits (rows with no
+  // prefix take row 0 and are never referenced)
   uint16_t* const pre_off = reinterpret_cast<uint16_t*>(csc + kG2Slots);
   const unsigned* const tmax = reinterpret_cast<const unsigned*>(tab32 + gm_max_offset(N, P, n));
   const int tchunks = rows * (kGmKC / 4);       // float4 per stage of the table
@@ -298,12 +301,12 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   const int sI = (tid >> 8) * 8, sJ = (tid >> 7) * 4;
   const int colI = cI0 + (tid & 255);
   const bool validI = colI < M;
-  const int preI = (validI ? colI / n - hiI0 : 0) * kG2TabPitch + sI;
+  const int preI = (validI ? colI / n - hiI0 : zrow) * kG2TabPitch + sI;
   const int lastI = ((P - 1) * n + (validI ? colI % n : 0)) * kG2TabPitch + sI;
   const int colJ = cJ0 + (tid & 127);
   const bool genJ = !diag;
   const bool validJ = genJ && colJ < M;
-  const int preJ = (gm_pre_rows_i(n, M) + (validJ ? colJ / n - hiJ0 : 0)) * kG2TabPitch + sJ;
+  const int preJ = (validJ ? gm_pre_rows_i(n, M) + colJ / n - hiJ0 : zrow) * kG2TabPitch + sJ;
   const int lastJ = ((P - 1) * n + (validJ ? colJ % n : 0)) * kG2TabPitch + sJ;
   const int jslot = diag ? h * kG2H : kGmT;  // B operand columns start here in a stage
 
@@ -340,16 +343,48 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
           float4{r.x * tsc, r.y * tsc, r.z * tsc, r.w * tsc};
     }
   };
-  // prefix rows of one stage from its 1-D tables: one (row, 4 samples) per
-  // thread; the table rows of each prefix (j*n + digit_j) are fixed for the
-  // work-group and were stored in pre_off at the start.
+  // prefix rows of one stage from its 1-D tables, in items of (row, 4
+  // samples).  Item tid's table-row offsets are held in registers for the
+  // whole work item; items past 512 (only when n <= 2) read them from
+  // pre_off in LDS.
   const int npre = gm_pre_rows(n, M);
+  int mp_off[GP_MAX_P - 1];
+  const bool mp_own = tid < npre * 4;
+  const int mp_dst = (tid >> 2) * kG2TabPitch + (tid & 3) * 4;
+  // (one unrolled body per factor count, so all reads issue before the products)
+  auto make_pre_k = [&](auto kc, const float* Tb, float* dst) {
+    constexpr int K = decltype(kc)::value;
+    float4 f[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; ++j) f[j] = *reinterpret_cast<const float4*>(Tb + mp_off[j]);
+    float4 v = float4{1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      v.x *= f[j].x;
+      v.y *= f[j].y;
+      v.z *= f[j].z;
+      v.w *= f[j].w;
+    }
+    *reinterpret_cast<float4*>(dst + mp_dst) = v;
+  };
   auto make_pre = [&](const float* Tb, float* dst) {
-    for (int u = tid; u < npre * 4; u += kG2Threads) {
-      const int pr = u >> 2, q4 = (u & 3) * 4;
-      const uint16_t* po = pre_off + pr * GP_MAX_P;
-      float4 v = float4{1.f, 1.f, 1.f, 1.f};
-      if (po[GP_MAX_P - 1] == 0) {
+    if (mp_own) {
+      switch (P - 1) {
+        case 0: make_pre_k(std::integral_constant<int, 0>{}, Tb, dst); break;
+        case 1: make_pre_k(std::integral_constant<int, 1>{}, Tb, dst); break;
+        case 2: make_pre_k(std::integral_constant<int, 2>{}, Tb, dst); break;
+        case 3: make_pre_k(std::integral_constant<int, 3>{}, Tb, dst); break;
+        case 4: make_pre_k(std::integral_constant<int, 4>{}, Tb, dst); break;
+        case 5: make_pre_k(std::integral_constant<int, 5>{}, Tb, dst); break;
+        case 6: make_pre_k(std::integral_constant<int, 6>{}, Tb, dst); break;
+        default: make_pre_k(std::integral_constant<int, 7>{}, Tb, dst); break;
+      }
+    }
+    if (npre * 4 > kG2Threads) {
+      for (int u = tid + kG2Threads; u < npre * 4; u += kG2Threads) {
+        const int pr = u >> 2, q4 = (u & 3) * 4;
+        const uint16_t* po = pre_off + pr * GP_MAX_P;
+        float4 v = float4{1.f, 1.f, 1.f, 1.f};
         for (int j = 0; j < P - 1; ++j) {
           const float4 f = *reinterpret_cast<const float4*>(Tb + po[j] * kG2TabPitch + q4);
           v.x *= f.x;
@@ -357,8 +392,8 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
           v.z *= f.z;
           v.w *= f.w;
         }
+        *reinterpret_cast<float4*>(dst + pr * kG2TabPitch + q4) = v;
       }
-      *reinterpret_cast<float4*>(dst + pr * kG2TabPitch + q4) = v;
     }
   };
   // generation inputs of one stage (prefix and last-factor values) into
@@ -386,20 +421,16 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
         v[4 * q + 2] = g.pa[q].z * g.la[q].z;
         v[4 * q + 3] = g.pa[q].w * g.la[q].w;
       }
-      if (!validI) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = 0.0f;
-      }
       gm_store<F16, 8>(v, D, tid & 255, sI);
     }
     {
       // J half (on diagonal tiles these slots are unused and get zeros)
+      // (invalid columns read the zero prefix row)
       float v[4];
       v[0] = g.pj.x * g.lj.x;
       v[1] = g.pj.y * g.lj.y;
       v[2] = g.pj.z * g.lj.z;
       v[3] = g.pj.w * g.lj.w;
-      if (!validJ) v[0] = v[1] = v[2] = v[3] = 0.0f;
       gm_store<F16, 4>(v, D, kGmT + (tid & 127), sJ);
     }
   };
@@ -419,7 +450,27 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
       po[j] = (uint16_t)(j * n + rem % n);
       rem /= n;
     }
-    po[GP_MAX_P - 1] = hi < 0 ? 1 : 0;
+  }
+  {
+    // the same rows for item tid, in registers
+    const int pr = tid >> 2;
+    int hi = -1;
+    if (pr < nhiI) hi = hiI0 + pr;
+    else if (pr >= gm_pre_rows_i(n, M) && pr - gm_pre_rows_i(n, M) < nhiJ) hi = hiJ0 + pr - gm_pre_rows_i(n, M);
+    int rem = hi < 0 ? 0 : hi;
+#pragma unroll
+    for (int j = GP_MAX_P - 2; j >= 0; --j) {
+      mp_off[j] = 0;
+      if (j < P - 1) {
+        mp_off[j] = (j * n + rem % n) * kG2TabPitch + (tid & 3) * 4;
+        rem /= n;
+      }
+    }
+  }
+  // zero rows of both prefix buffers
+  if (tid < kG2TabPitch) {
+    pr0[zrow * kG2TabPitch + tid] = 0.0f;
+    pr0[prs + zrow * kG2TabPitch + tid] = 0.0f;
   }
   for (int sl = tid; sl < kG2Slots; sl += kG2Threads) {
     const int c = sl < kGmT ? cI0 + sl : cJ0 + sl - kGmT;
