@@ -810,15 +810,16 @@ int64_t predict_mixed_part_elems(int64_t Ns, int M, int* groups_out) {
 // Per-column descriptor of the prediction, as LDS byte offsets for a
 // work-group of TN test points: .x the prefix row relative to the first
 // prefix of the column's stage of 16 (times TN*4), .y the 1-D table row of
-// the last factor, (p-1)*n + k (times TN*4).  Columns M .. ceil16(M)-1 point
-// at the zero row p*n.
+// the last factor, (p-1)*n + k (times TN*4).  Columns M .. ceil16(M)-1 take
+// prefix row 0 and last-factor row (p-1)*n: finite values, multiplied by the
+// zero padding columns of L^-1.
 __global__ void pdesc_kernel(int p, int n, int M, int TN, uint2* __restrict__ pdesc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int Mp = (int)ceil_div(M, kPmKC) * kPmKC;
   if (c >= Mp) return;
   const uint32_t rb = (uint32_t)TN * 4;
   if (c >= M) {
-    pdesc[c] = uint2{0u, (uint32_t)(p * n) * rb};
+    pdesc[c] = uint2{0u, (uint32_t)((p - 1) * n) * rb};
     return;
   }
   const int hrel = c / n - (c - c % kPmKC) / n;
@@ -842,7 +843,7 @@ __host__ __device__ inline int pm_pdig_entries(int p, int n, int M) {
   return e <= kPdigMax ? e : 0;
 }
 
-template <int TN, int P>
+template <int TN, int P, bool G>
 __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     const double* __restrict__ xs, int64_t Ns, int n, int M, const double* __restrict__ tab,
     const uint16_t* __restrict__ midx, const uint32_t* __restrict__ pdesc_words, const __bf16* __restrict__ lpieces,
@@ -882,17 +883,20 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     pdig[u] = (uint32_t)midx[(int64_t)hi * n * 8 + j] * (TN * 4);
   }
 
-  auto nstages = [&](int rb) { return (int)ceil_div(min(rb * kPmTR + kPmTR, M), kPmKC); };
+  const int Mc = (M + kPmKC - 1) / kPmKC;   // stages of the whole column range
+  auto nstages = [&](int rb) { return min((rb + 1) * (kPmTR / kPmKC), Mc); };
   auto advance = [&](int& rb, int& k) {
     if (++k == nstages(rb)) {
       ++rb;
       k = 0;
     }
   };
-  // prefixes of stage k (columns 16k .. 16k+15): PRE[r][i] for hi = 16k/n + r
+  // prefixes of stage k (columns 16k .. 16k+15): PRE[r][i] for hi = 16k/n + r,
+  // r over the stage's own prefixes only
   auto make_pre = [&](int k, float* dst) {
     const int hi0 = (k * kPmKC) / n;
-    for (int u = t; u < npr * TN; u += kPmThreads) {
+    const int nrow = (k * kPmKC + kPmKC - 1) / n - hi0 + 1;
+    for (int u = t; u < nrow * TN; u += kPmThreads) {
       const int r = __builtin_amdgcn_readfirstlane(u / TN);
       const int i = u % TN;
       int hi = hi0 + r;
@@ -918,14 +922,30 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   const int gp = t % TN;
   const int gq = __builtin_amdgcn_readfirstlane(t / TN);
   const char* const tf_gp = reinterpret_cast<const char*>(Tf + gp);
+  // G (CPT divides n): a thread's CPT columns share one prefix and take
+  // consecutive last-factor rows (CPT-aligned groups never cross a prefix),
+  // so one descriptor serves the group.  (Columns past M generate finite
+  // values that meet the zero columns of the padded L^-1.)
   auto gen_read = [&](int k, const float* pre, float* ga, float* gb) {
-    const uint2* dsc = pdesc + __builtin_amdgcn_readfirstlane(k * kPmKC + gq * C::CPT);
+    const int c0 = __builtin_amdgcn_readfirstlane(k * kPmKC + gq * C::CPT);
+    const uint2* dsc = pdesc + c0;
     const char* pre_gp = reinterpret_cast<const char*>(pre + gp);
+    if constexpr (G) {
+      const uint2 d = dsc[0];
+      const float pv = *reinterpret_cast<const float*>(pre_gp + d.x);
+      const float* lp = reinterpret_cast<const float*>(tf_gp + d.y);
 #pragma unroll
-    for (int u = 0; u < C::CPT; ++u) {
-      const uint2 d = dsc[u];
-      ga[u] = *reinterpret_cast<const float*>(pre_gp + d.x);
-      gb[u] = *reinterpret_cast<const float*>(tf_gp + d.y);
+      for (int u = 0; u < C::CPT; ++u) {
+        ga[u] = pv;
+        gb[u] = lp[u * TN];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < C::CPT; ++u) {
+        const uint2 d = dsc[u];
+        ga[u] = *reinterpret_cast<const float*>(pre_gp + d.x);
+        gb[u] = *reinterpret_cast<const float*>(tf_gp + d.y);
+      }
     }
   };
   auto gen_store = [&](const float* ga, const float* gb, __bf16* phi) {
@@ -1094,21 +1114,23 @@ static int predict_tn(int p, int n) { return predict_lds_bytes<256>(p, n) <= (si
 
 typedef void (*PredictKernel)(const double*, int64_t, int, int, const double*, const uint16_t*, const uint32_t*,
                               const __bf16*, int, double*);
-template <int TN>
+template <int TN, bool G>
 static PredictKernel predict_kernel_p(int p) {
   switch (p) {
-    case 1: return predict_var_mixed_kernel<TN, 1>;
-    case 2: return predict_var_mixed_kernel<TN, 2>;
-    case 3: return predict_var_mixed_kernel<TN, 3>;
-    case 4: return predict_var_mixed_kernel<TN, 4>;
-    case 5: return predict_var_mixed_kernel<TN, 5>;
-    case 6: return predict_var_mixed_kernel<TN, 6>;
-    case 7: return predict_var_mixed_kernel<TN, 7>;
-    default: return predict_var_mixed_kernel<TN, 8>;
+    case 1: return predict_var_mixed_kernel<TN, 1, G>;
+    case 2: return predict_var_mixed_kernel<TN, 2, G>;
+    case 3: return predict_var_mixed_kernel<TN, 3, G>;
+    case 4: return predict_var_mixed_kernel<TN, 4, G>;
+    case 5: return predict_var_mixed_kernel<TN, 5, G>;
+    case 6: return predict_var_mixed_kernel<TN, 6, G>;
+    case 7: return predict_var_mixed_kernel<TN, 7, G>;
+    default: return predict_var_mixed_kernel<TN, 8, G>;
   }
 }
-static PredictKernel predict_kernel_for(int TN, int p) {
-  return TN == 256 ? predict_kernel_p<256>(p) : predict_kernel_p<128>(p);
+// G: the thread's column group (CPT = 16 TN / 512 columns) divides n
+static PredictKernel predict_kernel_for(int TN, int p, bool G) {
+  if (TN == 256) return G ? predict_kernel_p<256, true>(p) : predict_kernel_p<256, false>(p);
+  return G ? predict_kernel_p<128, true>(p) : predict_kernel_p<128, false>(p);
 }
 
 void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, const double* tab,
@@ -1132,7 +1154,8 @@ void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, con
   const int rpg = (int)ceil_div(RB, want);
   groups = (int)ceil_div(RB, rpg);
   prof_mark(prof, GP_PH_PREDICT, true, s);
-  predict_kernel_for(TN, p)<<<dim3(ib, groups), dim3(kPmThreads), TN == 256 ? predict_lds_bytes<256>(p, n)
+  const bool G = n % (kPmKC * TN / kPmThreads) == 0;
+  predict_kernel_for(TN, p, G)<<<dim3(ib, groups), dim3(kPmThreads), TN == 256 ? predict_lds_bytes<256>(p, n)
                                                                              : predict_lds_bytes<128>(p, n), s>>>(
       xs, Ns, n, M, tab, midx, pdesc, linv_pieces, rpg, part);
   prof_mark(prof, GP_PH_PREDICT, false, s);
@@ -1157,8 +1180,11 @@ hipError_t configure_kernels() {
   }
   for (int p = 1; p <= GP_MAX_P; ++p)
     for (int tn : {128, 256}) {
-      e = hipFuncSetAttribute((const void*)predict_kernel_for(tn, p), hipFuncAttributeMaxDynamicSharedMemorySize, big);
-      if (e != hipSuccess) return e;
+      for (bool G : {false, true}) {
+        e = hipFuncSetAttribute((const void*)predict_kernel_for(tn, p, G), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                big);
+        if (e != hipSuccess) return e;
+      }
     }
   return e;
 }
