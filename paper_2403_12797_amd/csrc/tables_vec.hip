@@ -101,6 +101,7 @@ __device__ __forceinline__ void fill_tab_cf(const double* __restrict__ x, int64_
 // each element costs one multiply and one FMA.  Wave partials are summed in
 // fixed order.
 constexpr int kMvRows = 64;
+constexpr int kMvLd = kMvRows + 2;   // table row pitch: 16 rows x 2 samples hit distinct LDS banks
 
 __device__ __forceinline__ f64x4 mfma64m(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -114,6 +115,9 @@ __device__ __forceinline__ f64x4 mfma64m(double a, double b, f64x4 c) {
 // samples (four 16-row MFMA tiles, k padded to 4), scales U by the prefix
 // products of its lanes' (sample, prefix) pairs and accumulates per sample;
 // the 16 lanes of a sample and then the four waves are summed at the end.
+// The w block of a wave's next tile (16 n contiguous values) and its lanes'
+// prefix digit rows are fetched while the current tile is computed (the w
+// block through a per-wave double buffer in LDS).
 __global__ void __launch_bounds__(256) phi_matvec_kernel(const double* __restrict__ x, int64_t N, int p,
                                                          int n, int M, const double* __restrict__ tab,
                                                          const uint16_t* __restrict__ midx,
@@ -122,51 +126,87 @@ __global__ void __launch_bounds__(256) phi_matvec_kernel(const double* __restric
                                                          double* __restrict__ out) {
   extern __shared__ double sm[];
   double* T = sm;                                 // [p*n][64]
-  double* red = sm + p * n * kMvRows;             // [4][64]
-  const int64_t s0 = (int64_t)blockIdx.x * kMvRows;
-  fill_tab_sf<double>(x, N, p, n, s0, kMvRows, kMvRows, tab, T);
-  __syncthreads();
+  double* red = sm + p * n * kMvLd;               // [4][64]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wblk = 16 * n;                        // w values of one prefix tile
+  double* wb = red + 4 * kMvRows + wv * 2 * wblk; // this wave's [2][16 n] w buffers
+  const int64_t s0 = (int64_t)blockIdx.x * kMvRows;
+  fill_tab_sf<double>(x, N, p, n, s0, kMvRows, kMvLd, tab, T);
   const int H = M / n, nk = (n + 3) / 4;
-  const double* Tl = T + (p - 1) * n * kMvRows;   // rows of the last factor
+  const double* Tl = T + (p - 1) * n * kMvLd;     // rows of the last factor
+  // fetch tile ht's w block (zero past M) into buffer bf, and the digit rows
+  // of this lane's prefix in tile ht
+  auto fetch_w = [&](int ht, int bf) {
+    const int64_t base = (int64_t)ht * wblk;
+    for (int u = lane; u < wblk; u += 64) wb[bf * wblk + u] = base + u < M ? w[base + u] : 0.0;
+  };
+  auto fetch_dig = [&](int ht) {
+    const int hi = ht * 16 + (lane & 15);
+    return reinterpret_cast<const uint4*>(midx)[hi < H ? hi * n : 0];
+  };
   double acc[4][4];
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[rt][q] = 0.0;
+  int bf = 0;
+  uint4 dq_next = fetch_dig(wv);
+  if (wv * 16 < H) fetch_w(wv, 0);
+  __syncthreads();
   for (int ht = wv; ht * 16 < H; ht += 4) {
+    const uint4 dq = dq_next;
+    if ((ht + 4) * 16 < H) {
+      dq_next = fetch_dig(ht + 4);
+      fetch_w(ht + 4, bf ^ 1);
+    }
     const int hi = ht * 16 + (lane & 15);
     const bool hv = hi < H;
+    const double* wt = wb + bf * wblk;
     f64x4 d[4];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) d[rt] = f64x4{0.0, 0.0, 0.0, 0.0};
     for (int ks = 0; ks < nk; ++ks) {
       const int k = ks * 4 + (lane >> 4);
       const bool kv = k < n;
-      const double b = (hv && kv) ? w[(int64_t)hi * n + k] : 0.0;
+      const double b = kv ? wt[(lane & 15) * n + k] : 0.0;
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt) {
-        const double a = kv ? Tl[k * kMvRows + rt * 16 + (lane & 15)] : 0.0;
+        const double a = kv ? Tl[k * kMvLd + rt * 16 + (lane & 15)] : 0.0;
         d[rt] = mfma64m(a, b, d[rt]);
       }
     }
-    // 1-D table rows of the leading digits of this lane's prefix
+    // 1-D table rows of the leading digits of this lane's prefix, then
+    // PRE * U per (sample, prefix) with one unrolled body per factor count
     int rows[GP_MAX_P];
     {
-      const uint4 dq = reinterpret_cast<const uint4*>(midx)[hv ? hi * n : 0];
       const uint32_t dd[4] = {dq.x, dq.y, dq.z, dq.w};
 #pragma unroll
-      for (int j = 0; j < GP_MAX_P; ++j) rows[j] = (dd[j >> 1] >> ((j & 1) * 16)) & 0xffff;
+      for (int j = 0; j < GP_MAX_P; ++j) rows[j] = ((dd[j >> 1] >> ((j & 1) * 16)) & 0xffff) * kMvLd;
     }
+    auto scale_acc = [&](auto kc) {
+      constexpr int K = decltype(kc)::value;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+      for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int sm_i = rt * 16 + 4 * q + (lane >> 4);
-        double pre = hv ? 1.0 : 0.0;
-        for (int j = 0; j < p - 1; ++j) pre *= T[rows[j] * kMvRows + sm_i];
-        acc[rt][q] = fma(pre, d[rt][q], acc[rt][q]);
-      }
+        for (int q = 0; q < 4; ++q) {
+          const int sm_i = rt * 16 + 4 * q + (lane >> 4);
+          double pre = hv ? 1.0 : 0.0;
+#pragma unroll
+          for (int j = 0; j < K; ++j) pre *= T[rows[j] + sm_i];
+          acc[rt][q] = fma(pre, d[rt][q], acc[rt][q]);
+        }
+    };
+    switch (p - 1) {
+      case 0: scale_acc(std::integral_constant<int, 0>{}); break;
+      case 1: scale_acc(std::integral_constant<int, 1>{}); break;
+      case 2: scale_acc(std::integral_constant<int, 2>{}); break;
+      case 3: scale_acc(std::integral_constant<int, 3>{}); break;
+      case 4: scale_acc(std::integral_constant<int, 4>{}); break;
+      case 5: scale_acc(std::integral_constant<int, 5>{}); break;
+      case 6: scale_acc(std::integral_constant<int, 6>{}); break;
+      default: scale_acc(std::integral_constant<int, 7>{}); break;
+    }
+    bf ^= 1;
   }
   // sum over the 16 lanes that share a sample, then over the waves
 #pragma unroll
@@ -191,7 +231,7 @@ __global__ void __launch_bounds__(256) phi_matvec_kernel(const double* __restric
 void launch_phi_matvec(const double* x, int64_t N, int p, int n, int M, const double* tab, const uint16_t* midx,
                        const double* w, const double* y, double* out, hipStream_t s) {
   if (N <= 0) return;
-  const size_t lds = (size_t)(p * n * kMvRows + 4 * kMvRows) * sizeof(double);
+  const size_t lds = (size_t)(p * n * kMvLd + 4 * kMvRows + 4 * 2 * 16 * n) * sizeof(double);
   hipLaunchKernelGGL(phi_matvec_kernel, dim3(ceil_div(N, kMvRows)), dim3(256), lds, s, x, N, p, n, M, tab, midx,
                      w, y, out);
 }
@@ -207,6 +247,7 @@ void launch_phi_matvec(const double* x, int64_t N, int p, int n, int M, const do
 // in chunk order.
 constexpr int kTvChunk = 1024;
 constexpr int kTvKC = 16;
+constexpr int kTvLd = kTvKC + 1;     // table row pitch: rows of consecutive digits hit distinct LDS banks
 constexpr int kTvH = 256;
 
 __device__ __forceinline__ f64x4 mfma64v(double a, double b, f64x4 c) {
@@ -220,8 +261,8 @@ __global__ void __launch_bounds__(256) phiT_gemm_kernel(const double* __restrict
                                                         int64_t N, int p, int n, int M,
                                                         const double* __restrict__ tab, double* __restrict__ part) {
   extern __shared__ double sm[];
-  double* T = sm;                                 // [p*n][16] 1-D tables of the stage
-  double* PR = T + p * n * kTvKC;                 // [16][kTvH + 2]
+  double* T = sm;                                 // [p*n][17] 1-D tables of the stage
+  double* PR = T + p * n * kTvLd;                 // [16][kTvH + 2]
   double* W = PR + kTvKC * (kTvH + 2);            // [16][NB*16 + 2]
   const int WP = NB * 16 + 2;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -234,9 +275,13 @@ __global__ void __launch_bounds__(256) phiT_gemm_kernel(const double* __restrict
   int dig[GP_MAX_P];
   {
     int rem = hi < H ? hi : 0;
-    for (int j = p - 2; j >= 0; --j) {
-      dig[j] = rem % n;
-      rem /= n;
+#pragma unroll
+    for (int j = GP_MAX_P - 2; j >= 0; --j) {
+      dig[j] = 0;
+      if (j <= p - 2) {
+        dig[j] = rem % n;
+        rem /= n;
+      }
     }
   }
   f64x4 acc[4][NB];
@@ -251,24 +296,38 @@ __global__ void __launch_bounds__(256) phiT_gemm_kernel(const double* __restrict
     if (t < kTvKC * p) {
       const int i = t % kTvKC, j = t / kTvKC;
       const int64_t row = s0 + i;
-      double* o = T + (j * n) * kTvKC + i;
+      double* o = T + (j * n) * kTvLd + i;
       if (row < c1) {
         const double* dc = tab + kTabDim + j * kDimStride;
-        phi_1d<double, double>(x[row * p + j], dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, kTvKC);
+        phi_1d<double, double>(x[row * p + j], dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, kTvLd);
       } else {
-        for (int k = 0; k < n; ++k) o[k * kTvKC] = 0.0;
+        for (int k = 0; k < n; ++k) o[k * kTvLd] = 0.0;
       }
     }
     __syncthreads();
-    // PRE^T: thread = prefix, 16 samples
+    // PRE^T: thread = prefix, 16 samples (one unrolled body per factor count)
     {
       double pr[kTvKC];
 #pragma unroll
       for (int i = 0; i < kTvKC; ++i) pr[i] = (hi < H) ? 1.0 : 0.0;
-      for (int j = 0; j < p - 1; ++j) {
-        const double* Tj = T + (j * n + dig[j]) * kTvKC;
+      auto mul_rows = [&](auto kc) {
+        constexpr int K = decltype(kc)::value;
 #pragma unroll
-        for (int i = 0; i < kTvKC; ++i) pr[i] *= Tj[i];
+        for (int j = 0; j < K; ++j) {
+          const double* Tj = T + (j * n + dig[j]) * kTvLd;
+#pragma unroll
+          for (int i = 0; i < kTvKC; ++i) pr[i] *= Tj[i];
+        }
+      };
+      switch (p - 1) {
+        case 0: break;
+        case 1: mul_rows(std::integral_constant<int, 1>{}); break;
+        case 2: mul_rows(std::integral_constant<int, 2>{}); break;
+        case 3: mul_rows(std::integral_constant<int, 3>{}); break;
+        case 4: mul_rows(std::integral_constant<int, 4>{}); break;
+        case 5: mul_rows(std::integral_constant<int, 5>{}); break;
+        case 6: mul_rows(std::integral_constant<int, 6>{}); break;
+        default: mul_rows(std::integral_constant<int, 7>{}); break;
       }
 #pragma unroll
       for (int i = 0; i < kTvKC; ++i) PR[i * (kTvH + 2) + t] = pr[i];
@@ -277,7 +336,7 @@ __global__ void __launch_bounds__(256) phiT_gemm_kernel(const double* __restrict
     for (int u = t; u < kTvKC * NB * 16; u += 256) {
       const int i = u / (NB * 16), k = u % (NB * 16);
       const int64_t row = s0 + i;
-      W[i * WP + k] = (k < n && row < c1) ? T[((p - 1) * n + k) * kTvKC + i] * v[row] : 0.0;
+      W[i * WP + k] = (k < n && row < c1) ? T[((p - 1) * n + k) * kTvLd + i] * v[row] : 0.0;
     }
     __syncthreads();
     // MFMA: wave wv owns prefixes wv*64 .. +64 (4 blocks of 16)
@@ -325,7 +384,7 @@ void launch_phiT_vec(const double* x, const double* v, int64_t N, int p, int n, 
   const int64_t chunks = ceil_div(N, kTvChunk);
   const int H = M / n;
   const int NB = (int)ceil_div(n, 16);
-  const size_t lds = (size_t)(p * n * kTvKC + kTvKC * (kTvH + 2) + kTvKC * (NB * 16 + 2)) * sizeof(double);
+  const size_t lds = (size_t)(p * n * kTvLd + kTvKC * (kTvH + 2) + kTvKC * (NB * 16 + 2)) * sizeof(double);
   const dim3 grid(chunks, ceil_div(H, kTvH));
   switch (NB) {
     case 1: hipLaunchKernelGGL(phiT_gemm_kernel<1>, grid, dim3(256), lds, s, x, v, N, p, n, M, tab, part); break;
