@@ -891,9 +891,58 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
       k = 0;
     }
   };
+  // product of the leading factors j < jend of prefix hi at point i
+  auto pre_prod = [&](int hi, int i, int jend) {
+    float v = 1.0f;
+    if (npd) {
+      const char* tfi = reinterpret_cast<const char*>(Tf + i);
+#pragma unroll
+      for (int j = 0; j < P - 1; ++j)
+        if (j < jend) v *= *reinterpret_cast<const float*>(tfi + pdig[hi * (P - 1) + j]);
+    } else {
+      const uint4 dq = reinterpret_cast<const uint4*>(midx)[hi * n];
+      const uint32_t d[4] = {dq.x, dq.y, dq.z, dq.w};
+#pragma unroll
+      for (int j = 0; j < P - 1; ++j) {
+        const int row = (d[j >> 1] >> ((j & 1) * 16)) & 0xffff;
+        if (j < jend) v *= Tf[row * TN + i];
+      }
+    }
+    return v;
+  };
+  // G: one (row, point) item per thread (the stage's prefix rows times TN
+  // points fit in 512), and PRE[hi] = PRE2[hi / n] * phi_{p-2, hi % n}, with
+  // the product PRE2 of the factors before the last prefix digit kept in a
+  // register and formed again only when hi / n changes (uniform per wave).
+  int mp_q = -1;
+  float mp_pre2 = 1.0f;
+  auto make_pre_g = [&](int k, float* dst) {
+    const int hi0 = (k * kPmKC) / n;
+    const int nrow = (k * kPmKC + kPmKC - 1) / n - hi0 + 1;
+    const int r = __builtin_amdgcn_readfirstlane(t / TN);
+    const int i = t % TN;
+    if (r < nrow) {
+      int hi = hi0 + r;
+      if (hi * n >= M) hi = 0;   // past the last column: never referenced
+      float v = 1.0f;
+      if constexpr (P > 1) {
+        const int q = hi / n;
+        if (q != mp_q) {
+          mp_q = q;
+          mp_pre2 = pre_prod(hi, i, P - 2);
+        }
+        v = mp_pre2 * Tf[((P - 2) * n + hi % n) * TN + i];
+      }
+      dst[r * TN + i] = v;
+    }
+  };
   // prefixes of stage k (columns 16k .. 16k+15): PRE[r][i] for hi = 16k/n + r,
   // r over the stage's own prefixes only
   auto make_pre = [&](int k, float* dst) {
+    if constexpr (G) {
+      make_pre_g(k, dst);
+      return;
+    }
     const int hi0 = (k * kPmKC) / n;
     const int nrow = (k * kPmKC + kPmKC - 1) / n - hi0 + 1;
     for (int u = t; u < nrow * TN; u += kPmThreads) {
