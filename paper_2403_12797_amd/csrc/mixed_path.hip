@@ -1027,111 +1027,142 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   const __bf16* const lbase1 = lbase0 + PP;                                   // term 1
   // (rows are padded to a multiple of 256 with zeros; a look-ahead past the
   // last row block re-reads the last one)
-  auto lin_load = [&](int rb, int k, uint4* reg) {
+  auto lin_load = [&](int rb, int k, uint4& r0, uint4& r1) {
     const int64_t off = (int64_t)min(rb, RB - 1) * kPmTR * LP + k * kPmKC;
-    reg[0] = *reinterpret_cast<const uint4*>(lbase0 + off);
-    reg[1] = *reinterpret_cast<const uint4*>(lbase1 + off);
+    r0 = *reinterpret_cast<const uint4*>(lbase0 + off);
+    r1 = *reinterpret_cast<const uint4*>(lbase1 + off);
   };
-  auto lin_store = [&](__bf16* lin, const uint4* reg) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int q = t + u * kPmThreads;
-      const int term = q >> 9, r = (q >> 1) & 255, half = q & 1;
-      *reinterpret_cast<uint4*>(lin + (term * kPmTR + r) * kPmPitch + half * 8) = reg[u];
-    }
+  // thread t stores its two uint4 at (term t >> 9 = 0, row (t >> 1) & 255,
+  // half t & 1) and the same place of term 1
+  auto lin_store = [&](__bf16* lin, const uint4& r0, const uint4& r1) {
+    const int r = (t >> 1) & 255, half = t & 1;
+    *reinterpret_cast<uint4*>(lin + r * kPmPitch + half * 8) = r0;
+    *reinterpret_cast<uint4*>(lin + (kPmTR + r) * kPmPitch + half * 8) = r1;
   };
 
   __syncthreads();  // tables ready
   if (rb0 < rb1) {
-    uint4 lreg[2];
-    // prologue: prefixes of the first stage, then its Phi_* and L^-1 slab
-    // into buffer 0 and the second stage's prefixes into prefix buffer 1
-    make_pre(0, pre0);
-    __syncthreads();
-    gen(0, pre0, buf0);
-    lin_load(rb0, 0, lreg);
-    lin_store(buf0 + C::PHI, lreg);
-    {
-      int nrb = rb0, nk = 0;
-      advance(nrb, nk);
-      if (nrb < rb1) make_pre(nk, pre0 + npr * TN);
-    }
-    __syncthreads();
-    int b = 0, pb = 1;   // stage buffer of the current stage; prefix buffer of the next
-    for (int rb = rb0; rb < rb1; ++rb) {
-      const int ns = nstages(rb);
-      f32x16 acc[2][C::CB];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int cb = 0; cb < C::CB; ++cb)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) acc[a][cb][r] = 0.0f;
-      for (int k = 0; k < ns; ++k) {
-        int nrb = rb, nk = k;
-        advance(nrb, nk);
-        int n2rb = nrb, n2k = nk;
-        advance(n2rb, n2k);
-        const bool has_next = nrb < rb1, has_next2 = n2rb < rb1;
-        // (past the last stage the next-stage work reads valid memory and
-        // writes a buffer that is not read again)
-        lin_load(nrb, nk, lreg);
-        float ga[C::CPT], gb[C::CPT];
-        gen_read(nk, pre0 + pb * npr * TN, ga, gb);
-        const __bf16* PHs = buf0 + b * (C::PHI + C::LIN);
-        const __bf16* LNs = PHs + C::PHI;
-        bf16x8 aop[2][2], bop[C::CB][2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int q = 0; q < 2; ++q)
-            aop[a][q] = *reinterpret_cast<const bf16x8*>(
-                PHs + (q * TN + wp * 64 + a * 32 + (lane & 31)) * kPmPitch + (lane >> 5) * 8);
-#pragma unroll
-        for (int cb = 0; cb < C::CB; ++cb)
-#pragma unroll
-          for (int q = 0; q < 2; ++q)
-            bop[cb][q] = *reinterpret_cast<const bf16x8*>(
-                LNs + (q * kPmTR + wr * (kPmTR / C::WR) + cb * 32 + (lane & 31)) * kPmPitch + (lane >> 5) * 8);
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int cb = 0; cb < C::CB; ++cb) acc[a][cb] = mfma_bf16(aop[a][1], bop[cb][0], acc[a][cb]);
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int cb = 0; cb < C::CB; ++cb) acc[a][cb] = mfma_bf16(aop[a][0], bop[cb][1], acc[a][cb]);
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int cb = 0; cb < C::CB; ++cb) acc[a][cb] = mfma_bf16(aop[a][0], bop[cb][0], acc[a][cb]);
-        {
-          __bf16* nb = buf0 + (b ^ 1) * (C::PHI + C::LIN);
-          gen_store(ga, gb, nb);
-          lin_store(nb + C::PHI, lreg);
-        }
-        if (has_next2) make_pre(n2k, pre0 + (pb ^ 1) * npr * TN);
-        __syncthreads();
-        b ^= 1;
-        pb ^= 1;
+    // Stage iterator (rb, k): column stage k of row block rb.  Past the last
+    // stage it keeps to valid descriptors, prefixes and (clamped) L^-1 rows.
+    struct It {
+      int rb, k, ns;
+    };
+    auto adv = [&](It& a) {
+      if (++a.k == a.ns) {
+        ++a.rb;
+        a.k = 0;
+        a.ns = nstages(a.rb);
       }
-      // squares of this column block, summed over the wave's columns
+    };
+    int S = 0;
+    for (int rb = rb0; rb < rb1; ++rb) S += nstages(rb);
+    It s0{rb0, 0, nstages(rb0)};
+    It s1 = s0;
+    adv(s1);
+    It s2 = s1;
+    adv(s2);
+    It s3 = s2;
+    adv(s3);
+    // prologue: prefixes of stages 0 and 1, Phi_* and L^-1 slab of stage 0 in
+    // buffer 0, the slabs of stages 1 and 2 in registers
+    uint4 la0, la1, lb0, lb1;
+    make_pre(s0.k, pre0);
+    lin_load(s0.rb, s0.k, la0, la1);
+    __syncthreads();
+    gen(s0.k, pre0, buf0);
+    lin_store(buf0 + C::PHI, la0, la1);
+    lin_load(s1.rb, s1.k, lb0, lb1);
+    lin_load(s2.rb, s2.k, la0, la1);
+    if (s1.rb < rb1) make_pre(s1.k, pre0 + npr * TN);
+    __syncthreads();
+    f32x16 acc[2][C::CB];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int cb = 0; cb < C::CB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[a][cb][r] = 0.0f;
+    int b = 0, pb = 1;   // stage buffer of the current stage; prefix buffer of the next
+    // One stage: MFMAs on stage s0 (buffer b), Phi_* of s1 generated into
+    // buffer b^1 with the L^-1 slab of s1 (from R, which is then refilled with
+    // the slab of s3, two stages ahead), prefixes of s2.
+    auto stage = [&](uint4& R0, uint4& R1) __attribute__((always_inline)) {
+      const bool pre_next = s2.rb < rb1;
+      float* const pdst = pre0 + (pb ^ 1) * npr * TN;
+      float ga[C::CPT], gb[C::CPT];
+      gen_read(s1.k, pre0 + pb * npr * TN, ga, gb);
+      const __bf16* PHs = buf0 + b * (C::PHI + C::LIN);
+      const __bf16* LNs = PHs + C::PHI;
+      bf16x8 aop[2][2], bop[C::CB][2];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          float s2 = 0.0f;
+        for (int q = 0; q < 2; ++q)
+          aop[a][q] = *reinterpret_cast<const bf16x8*>(
+              PHs + (q * TN + wp * 64 + a * 32 + (lane & 31)) * kPmPitch + (lane >> 5) * 8);
 #pragma unroll
-          for (int cb = 0; cb < C::CB; ++cb) s2 = fmaf(acc[a][cb][r], acc[a][cb][r], s2);
-          double v = (double)s2;
-          v += __shfl_xor(v, 1);
-          v += __shfl_xor(v, 2);
-          v += __shfl_xor(v, 4);
-          v += __shfl_xor(v, 8);
-          v += __shfl_xor(v, 16);
-          if ((lane & 31) == 0) ssw[wr * TN + wp * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] += v;
-        }
+      for (int cb = 0; cb < C::CB; ++cb)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          bop[cb][q] = *reinterpret_cast<const bf16x8*>(
+              LNs + (q * kPmTR + wr * (kPmTR / C::WR) + cb * 32 + (lane & 31)) * kPmPitch + (lane >> 5) * 8);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int cb = 0; cb < C::CB; ++cb) acc[a][cb] = mfma_bf16(aop[a][1], bop[cb][0], acc[a][cb]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int cb = 0; cb < C::CB; ++cb) acc[a][cb] = mfma_bf16(aop[a][0], bop[cb][1], acc[a][cb]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int cb = 0; cb < C::CB; ++cb) acc[a][cb] = mfma_bf16(aop[a][0], bop[cb][0], acc[a][cb]);
+      {
+        __bf16* nb = buf0 + (b ^ 1) * (C::PHI + C::LIN);
+        gen_store(ga, gb, nb);
+        lin_store(nb + C::PHI, R0, R1);
+        lin_load(s3.rb, s3.k, R0, R1);
+      }
+      if (pre_next) make_pre(s2.k, pdst);
+      if (s0.k == s0.ns - 1) {
+        // squares of this column block, summed over the wave's columns
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            float s2v = 0.0f;
+#pragma unroll
+            for (int cb = 0; cb < C::CB; ++cb) s2v = fmaf(acc[a][cb][r], acc[a][cb][r], s2v);
+            double v = (double)s2v;
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 8);
+            v += __shfl_xor(v, 16);
+            if ((lane & 31) == 0) ssw[wr * TN + wp * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] += v;
+          }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int cb = 0; cb < C::CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][cb][r] = 0.0f;
+      }
+      __syncthreads();
+      b ^= 1;
+      pb ^= 1;
+      s0 = s1;
+      s1 = s2;
+      s2 = s3;
+      adv(s3);
+    };
+    // stages alternate the two slab registers
+    for (int q = 0; q + 1 < S; q += 2) {
+      stage(lb0, lb1);
+      stage(la0, la1);
     }
+    if (S & 1) stage(lb0, lb1);
   }
   __syncthreads();
   if (t < TN && i0 + t < Ns) {
