@@ -187,69 +187,85 @@ void launch_gram_f64(const double* x, int64_t N, int p, int n, int M, const doub
 constexpr int kNb = kCholNb;
 constexpr int kNbLd = kNb + 1;
 
-__global__ void __launch_bounds__(256) potrf_diag_kernel(double* __restrict__ A, int M, int k0,
-                                                         double* __restrict__ Dinv, int* __restrict__ info) {
+constexpr int kPfThreads = 512;
+constexpr int kPfTpr = 8;                      // threads per row of W
+constexpr int kPfCols = 2 * kNb / kPfTpr;      // 16 consecutive columns of W per thread
+constexpr int kPfPitch = kPfCols + 2;          // padded so the 8 column groups hit distinct banks
+
+__global__ void __launch_bounds__(kPfThreads) potrf_diag_kernel(double* __restrict__ A, int M, int k0,
+                                                                double* __restrict__ Dinv, int* __restrict__ info) {
   // Factor the diagonal block B = L L^T and form X = L^-1 together, by row
   // elimination on W = [B | I] (64 x 128): step j takes the pivot
   // sqrt(W[j][j]), then every row i > j subtracts l_ij / piv times the
   // pivot row (l_ij = W[i][j] / piv = L[i][j]) and row j is divided by the
   // pivot.  The trailing part of B stays symmetric, so the pivot row also
   // supplies column j, and only the pivot row is exchanged (through LDS,
-  // double-buffered).  Afterwards the right half of W is X.  Thread t owns
-  // row i = t/4 and the 32 columns t%4 + 4q of W in registers.  Rows and
+  // double-buffered, column groups padded).  Afterwards the right half of W
+  // is X.  Thread t owns row i = t/8 and the 16 consecutive columns
+  // 16 (t%8) .. +16 of W in registers (groups 0-3 in B, 4-7 in I).  Rows and
   // columns past the matrix are the identity.
-  __shared__ double prow[2][2 * kNb];
+  __shared__ double prow[2][kPfTpr * kPfPitch];
   __shared__ double Ls[kNb * kNbLd];
   if (*info) return;
   const int t = threadIdx.x, wv = t >> 6;
   const int nb = min(kNb, M - k0);
-  const int i = t >> 2, c0 = t & 3;
-  double w[32];
+  const int i = t / kPfTpr, g = t % kPfTpr;
+  const bool inB = g < kPfTpr / 2;
+  auto pidx = [](int c) { return (c / kPfCols) * kPfPitch + c % kPfCols; };
+  double w[kPfCols];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = c0 + 4 * q;
-    const int r = i > c ? i : c, cc = i > c ? c : i;   // lower triangle of the block
-    w[q] = (i < nb && c < nb) ? A[(int64_t)(k0 + r) * M + k0 + cc] : (i == c ? 1.0 : 0.0);
-    w[16 + q] = (i == c) ? 1.0 : 0.0;
+  for (int m = 0; m < kPfCols; ++m) {
+    const int c = g * kPfCols + m;                    // column of W
+    if (inB) {
+      const int r = i > c ? i : c, cc = i > c ? c : i;  // lower triangle of the block
+      w[m] = (i < nb && c < nb) ? A[(int64_t)(k0 + r) * M + k0 + cc] : (i == c ? 1.0 : 0.0);
+    } else {
+      w[m] = (i == c - kNb) ? 1.0 : 0.0;
+    }
   }
   if (i == 0) {
 #pragma unroll
-    for (int q = 0; q < 32; ++q) prow[0][c0 + 4 * q] = w[q];
+    for (int m = 0; m < kPfCols; ++m) prow[0][g * kPfPitch + m] = w[m];
   }
   for (int j = 0; j < kNb; ++j) {
     __syncthreads();
     const int bs = j & 1;
-    const double d = prow[bs][j];
+    const double d = prow[bs][pidx(j)];
     if (!(d > 0.0) || !isfinite(d)) {   // same value in every thread
       if (t == 0) *info = k0 + j + 1;
       return;
     }
     const double piv = sqrt(d), rp = 1.0 / piv;
-    if (wv * 16 + 15 >= j) {            // waves whose rows are all above j are done
+    if (wv * (64 / kPfTpr) + (64 / kPfTpr) - 1 >= j) {   // waves whose rows are all above j are done
       if (i == j) {
 #pragma unroll
-        for (int q = 0; q < 32; ++q) w[q] *= rp;
+        for (int m = 0; m < kPfCols; ++m) w[m] *= rp;
       } else {
-        const double l = (i > j) ? prow[bs][i] * rp : 0.0;
+        const double l = (i > j) ? prow[bs][pidx(i)] * rp : 0.0;
         const double lr = l * rp;
+        const double* pr = &prow[bs][g * kPfPitch];
 #pragma unroll
-        for (int q = 0; q < 32; ++q) w[q] = fma(-lr, prow[bs][c0 + 4 * q], w[q]);
-        if (c0 == 0 && i > j) Ls[i * kNbLd + j] = l;
+        for (int m = 0; m < kPfCols; ++m) w[m] = fma(-lr, pr[m], w[m]);
+        if (g == 0 && i > j) Ls[i * kNbLd + j] = l;
       }
-      if (i == j && c0 == 0) Ls[j * kNbLd + j] = piv;
+      if (i == j && g == 0) Ls[j * kNbLd + j] = piv;
       if (i == j + 1) {
 #pragma unroll
-        for (int q = 0; q < 32; ++q) prow[bs ^ 1][c0 + 4 * q] = w[q];
+        for (int m = 0; m < kPfCols; ++m) prow[bs ^ 1][g * kPfPitch + m] = w[m];
       }
     }
   }
   __syncthreads();
   double* D = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = c0 + 4 * q;
-    D[i * kNb + c] = (i < nb && c < nb && c <= i) ? w[16 + q] : 0.0;
-    if (i < nb && c < nb) A[(int64_t)(k0 + i) * M + k0 + c] = (c <= i) ? Ls[i * kNbLd + c] : 0.0;
+  for (int m = 0; m < kPfCols; ++m) {
+    if (inB) {
+      const int c = g * kPfCols + m;
+      if (i < nb && c < nb) A[(int64_t)(k0 + i) * M + k0 + c] = (c <= i) ? Ls[i * kNbLd + c] : 0.0;
+    } else {
+      const int c = g * kPfCols + m - kNb;
+      D[i * kNb + c] = (i < nb && c < nb && c <= i) ? w[m] : 0.0;
+    }
   }
 }
 
@@ -356,7 +372,7 @@ __global__ void __launch_bounds__(256) syrk_trailing_kernel(double* __restrict__
 
 void launch_cholesky(double* A, int M, double* Dinv, int* info, hipStream_t s) {
   for (int k0 = 0; k0 < M; k0 += kNb) {
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, A, M, k0, Dinv, info);
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(kPfThreads), 0, s, A, M, k0, Dinv, info);
     const int rest = M - k0 - kNb;
     if (rest <= 0) break;
     const int tb = (int)ceil_div(rest, kNb);
