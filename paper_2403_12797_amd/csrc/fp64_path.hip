@@ -318,10 +318,69 @@ __global__ void __launch_bounds__(256) trsm_panel_kernel(double* __restrict__ A,
       }
 }
 
+// BT: B is given transposed, as Bt[n][k] = B[k][n] with row pitch ldb.
+template <bool BT = false>
+__device__ __forceinline__ void tile_gemm64(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+                                            int64_t ldb, int kb, int ke, int mv, int nv, int kv, double* As,
+                                            double* Bs, f64x4 (&acc)[2][2]) {
+  // K steps of 16; the next step's tiles are fetched into registers while
+  // the current one is multiplied (four A and four B values per thread).
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int wr = wv >> 1, wc = wv & 1;
+  double ra[4], rb[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int u = t + r * 256;
+      const int m = u >> 4, k = u & 15;
+      ra[r] = (m < mv && k0 + k < kv && k0 + k < ke) ? A[(int64_t)m * lda + k0 + k] : 0.0;
+      if constexpr (BT) {
+        rb[r] = (m < nv && k0 + k < kv && k0 + k < ke) ? B[(int64_t)m * ldb + k0 + k] : 0.0;   // Bt[n = m][k]
+      } else {
+        const int kk = u >> 6, nn = u & 63;
+        rb[r] = (nn < nv && k0 + kk < kv && k0 + kk < ke) ? B[(int64_t)(k0 + kk) * ldb + nn] : 0.0;
+      }
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    __syncthreads();
+    // A tile 64 x 16 -> As[m][k] (pitch 17), B tile 16 x 64 -> Bs[k][n] (pitch 66)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int u = t + r * 256;
+      As[(u >> 4) * 17 + (u & 15)] = ra[r];
+      if constexpr (BT)
+        Bs[(u & 15) * 66 + (u >> 4)] = rb[r];
+      else
+        Bs[(u >> 6) * 66 + (u & 63)] = rb[r];
+    }
+    __syncthreads();
+    if (k0 + 16 < ke) fetch(k0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = kk * 4 + (lane >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        av[q] = As[(wr * 32 + q * 16 + (lane & 15)) * 17 + k];
+        bv[q] = Bs[k * 66 + wc * 32 + q * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) syrk_trailing_kernel(double* __restrict__ A, int M, int k0,
                                                             const int* __restrict__ info) {
-  __shared__ double PR[kNb * kNbLd];
-  __shared__ double PC[kNb * kNbLd];
+  // Trailing tile (R, C), C <= R, of the lower part: A[R][C] -= L_R L_C^T with
+  // L_R, L_C the 64 panel columns of rows R and C, on the pipelined 64x64
+  // FP64-MFMA tile product (L_C read transposed).
+  __shared__ double As[64 * 17];
+  __shared__ double Bs[16 * 66];
   if (*info) return;
   int tile = blockIdx.x, R = 0;
   while (tile > R) {
@@ -331,33 +390,14 @@ __global__ void __launch_bounds__(256) syrk_trailing_kernel(double* __restrict__
   const int C = tile;
   const int base = k0 + kNb;
   const int R0 = base + R * kNb, C0 = base + C * kNb;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  for (int idx = t; idx < kNb * kNb; idx += 256) {
-    const int i = idx / kNb, c = idx % kNb;
-    PR[i * kNbLd + c] = (R0 + i < M) ? A[(int64_t)(R0 + i) * M + k0 + c] : 0.0;
-    PC[i * kNbLd + c] = (C0 + i < M) ? A[(int64_t)(C0 + i) * M + k0 + c] : 0.0;
-  }
-  __syncthreads();
-  const int wr = wv >> 1, wc = wv & 1;
   f64x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int kk = 0; kk < kNb / 4; ++kk) {
-    const int k = kk * 4 + (lane >> 4);
-    double av[2], bv[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      av[q] = PR[(wr * 32 + q * 16 + (lane & 15)) * kNbLd + k];
-      bv[q] = PC[(wc * 32 + q * 16 + (lane & 15)) * kNbLd + k];
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
-  }
+  tile_gemm64<true>(A + (int64_t)R0 * M + k0, M, A + (int64_t)C0 * M + k0, M, 0, kNb, M - R0, M - C0, kNb, As, Bs,
+                    acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wr = wv >> 1, wc = wv & 1;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -401,38 +441,6 @@ __global__ void trtri_diag_kernel(const double* __restrict__ Dinv, double* __res
 // One 64x64 output tile of C = sum_k A[m][k] B[k][n] with A, B row-major in
 // global memory (lda, ldb), k in [kb, ke), rows m >= mv / columns n >= nv and
 // k >= kv read as zero.  4 waves, each a 32x32 quarter (2x2 MFMA blocks).
-__device__ __forceinline__ void tile_gemm64(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
-                                            int64_t ldb, int kb, int ke, int mv, int nv, int kv, double* As,
-                                            double* Bs, f64x4 (&acc)[2][2]) {
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wr = wv >> 1, wc = wv & 1;
-  for (int k0 = kb; k0 < ke; k0 += 16) {
-    __syncthreads();
-    // A tile 64 x 16 -> As[m][k] (pitch 17), B tile 16 x 64 -> Bs[k][n] (pitch 66)
-    for (int u = t; u < 64 * 16; u += 256) {
-      const int m = u >> 4, k = u & 15;
-      As[m * 17 + k] = (m < mv && k0 + k < kv && k0 + k < ke) ? A[(int64_t)m * lda + k0 + k] : 0.0;
-      const int kk = u >> 6, nn = u & 63;
-      Bs[kk * 66 + nn] = (nn < nv && k0 + kk < kv && k0 + kk < ke) ? B[(int64_t)(k0 + kk) * ldb + nn] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = kk * 4 + (lane >> 4);
-      double av[2], bv[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        av[q] = As[(wr * 32 + q * 16 + (lane & 15)) * 17 + k];
-        bv[q] = Bs[k * 66 + wc * 32 + q * 16 + (lane & 15)];
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
-    }
-  }
-}
-
 // T[g] = L21 X11 for pair g of width b (T is b x b, row-major, per pair).
 __global__ void __launch_bounds__(256) trtri_merge_t_kernel(const double* __restrict__ L,
                                                             const double* __restrict__ X, double* __restrict__ T,
