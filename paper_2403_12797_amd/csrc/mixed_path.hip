@@ -180,7 +180,7 @@ constexpr int kG2Flush = 16;                                // stages per MFMA c
 constexpr int kG2Slots = kGmT + kG2H;                       // 384 column slots per stage
 constexpr int kG2SlotPitch = kGmKC + 8;                     // f16 per slot (16 samples + pad)
 constexpr int kG2TabPitch = kGmKC + 4;                      // floats per table / prefix row (16 + pad)
-constexpr int kGmChunk = 16384;                             // samples per FP32 partial
+constexpr int kGmChunk = 32768;                             // samples per FP32 partial
 constexpr int64_t kGmPartCap = 8ll << 30;                   // bytes of partials per pass
 // 16-bit elements per stage buffer: [term][slot][sample]
 __host__ __device__ constexpr int gm_stage_elems(bool f16) { return (f16 ? 2 : 3) * kG2Slots * kG2SlotPitch; }
@@ -190,7 +190,7 @@ GramPlan gram_mixed_plan(int64_t N, int M, int chunk) {
   g.T = (int)ceil_div(M, kGmT);
   g.ntiles = g.T * (g.T + 1) / 2;
   if (chunk <= 0) {
-    // enough work items to fill the GPU several times over: chunks of 1024..16384 samples
+    // enough work items to fill the GPU several times over: chunks of 1024..32768 samples
     const int64_t want = ceil_div(N * 2 * g.ntiles, 1024);
     chunk = (int)std::min<int64_t>(kGmChunk, std::max<int64_t>(1024, ceil_div(want, kGmKC) * kGmKC));
   }
