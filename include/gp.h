@@ -160,7 +160,8 @@ gp_status gp_predict_batch(gp_ctx *ctx, int32_t count, const gp_model *const *mo
                            const double *const *xs, const int64_t *Ns, double *const *mean,
                            double *const *var, void *stream);
 
-/* Autotuner: time the split-BF16 Gram kernel for (p, n, N) on synthetic
+/* Autotuner: time the mixed Gram kernel (split-FP16 scheme; the chunk it
+ * picks serves both mixed modes) for (p, n, N) on synthetic
  * inputs at several sample-chunk lengths and keep the fastest for later fits
  * of this context with the same p, n and floor(log2 N) (and in the file named
  * by the environment variable MGP_TUNE_CACHE, read at context creation).
