@@ -145,8 +145,9 @@ gp_status gp_model_get(const gp_model *model, int32_t what, double *host_out, in
 
 /* Batched fit of `count` independent problems (uneven N, p, n allowed):
  * params/x/y/N/out_models are arrays of length count (x[k], y[k] device
- * arrays as in gp_fit).  The mixed-precision problems share one persistent
- * Gram launch over all their tiles (work list, longest first); the whole
+ * arrays as in gp_fit).  The mixed-precision problems of each Gram scheme
+ * share one persistent Gram launch over all their tiles (work list, longest
+ * first); the whole
  * batch runs as one captured HIP graph.  Waits for completion.  Each
  * out_models[k] is a new model; on an error the failing problem's model is
  * NULL and the first error is returned (other models stay valid).
