@@ -269,55 +269,9 @@ __global__ void __launch_bounds__(kPfThreads) potrf_diag_kernel(double* __restri
   }
 }
 
-// Panel below the diagonal block: L21 = B21 L11^-T = B21 X^T as one 64x64x64
-// FP64-MFMA product per 64-row block (X lower, zero above the diagonal).
-__global__ void __launch_bounds__(256) trsm_panel_kernel(double* __restrict__ A, int M, int k0,
-                                                         const double* __restrict__ Dinv,
-                                                         const int* __restrict__ info) {
-  __shared__ double Bs[kNb * kNbLd];        // B21 rows [m][k]
-  __shared__ double Xt[kNb * (kNb + 2)];    // X^T [k][n] = X[n][k]
-  if (*info) return;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wr = wv >> 1, wc = wv & 1;
-  const int R0 = k0 + kNb + blockIdx.x * kNb;
-  const double* Dk = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
-  for (int u = t; u < kNb * kNb; u += 256) {
-    const int r = u >> 6, c = u & 63;
-    Bs[r * kNbLd + c] = (R0 + r < M) ? A[(int64_t)(R0 + r) * M + k0 + c] : 0.0;
-    Xt[c * (kNb + 2) + r] = Dk[u];
-  }
-  __syncthreads();
-  f64x4 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int kk = 0; kk < kNb / 4; ++kk) {
-    const int k = kk * 4 + (lane >> 4);
-    double av[2], bv[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      av[q] = Bs[(wr * 32 + q * 16 + (lane & 15)) * kNbLd + k];
-      bv[q] = Xt[k * (kNb + 2) + wc * 32 + q * 16 + (lane & 15)];
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
-  }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = R0 + wr * 32 + a * 16 + 4 * q + (lane >> 4);
-        const int col = k0 + wc * 32 + b * 16 + (lane & 15);
-        if (row < M) A[(int64_t)row * M + col] = acc[a][b][q];
-      }
-}
-
+// One 64x64 output tile of C = sum_k A[m][k] B[k][n] with A, B row-major in
+// global memory (lda, ldb), k in [kb, ke), rows m >= mv / columns n >= nv and
+// k >= kv read as zero.  4 waves, each a 32x32 quarter (2x2 MFMA blocks).
 // BT: B is given transposed, as Bt[n][k] = B[k][n] with row pitch ldb.
 template <bool BT = false>
 __device__ __forceinline__ void tile_gemm64(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
@@ -372,6 +326,37 @@ __device__ __forceinline__ void tile_gemm64(const double* __restrict__ A, int64_
         for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
     }
   }
+}
+
+// Panel below the diagonal block: L21 = B21 L11^-T = B21 X^T as one 64x64x64
+// FP64-MFMA product per 64-row block (X lower, zero above the diagonal).
+__global__ void __launch_bounds__(256) trsm_panel_kernel(double* __restrict__ A, int M, int k0,
+                                                         const double* __restrict__ Dinv,
+                                                         const int* __restrict__ info) {
+  __shared__ double As[64 * 17];
+  __shared__ double Bs[16 * 66];
+  if (*info) return;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int wr = wv >> 1, wc = wv & 1;
+  const int R0 = k0 + kNb + blockIdx.x * kNb;
+  const double* Dk = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // B21 X^T: X (row-major, lower) is the transposed B operand
+  tile_gemm64<true>(A + (int64_t)R0 * M + k0, M, Dk, kNb, 0, kNb, M - R0, kNb, kNb, As, Bs, acc);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = R0 + wr * 32 + a * 16 + 4 * q + (lane >> 4);
+        const int col = k0 + wc * 32 + b * 16 + (lane & 15);
+        if (row < M) A[(int64_t)row * M + col] = acc[a][b][q];
+      }
 }
 
 __global__ void __launch_bounds__(256) syrk_trailing_kernel(double* __restrict__ A, int M, int k0,
@@ -438,9 +423,6 @@ __global__ void trtri_diag_kernel(const double* __restrict__ Dinv, double* __res
   }
 }
 
-// One 64x64 output tile of C = sum_k A[m][k] B[k][n] with A, B row-major in
-// global memory (lda, ldb), k in [kb, ke), rows m >= mv / columns n >= nv and
-// k >= kv read as zero.  4 waves, each a 32x32 quarter (2x2 MFMA blocks).
 // T[g] = L21 X11 for pair g of width b (T is b x b, row-major, per pair).
 __global__ void __launch_bounds__(256) trtri_merge_t_kernel(const double* __restrict__ L,
                                                             const double* __restrict__ X, double* __restrict__ T,
