@@ -916,9 +916,13 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   // register and formed again only when hi / n changes (uniform per wave).
   int mp_q = -1;
   float mp_pre2 = 1.0f;
+  // (divisions by n as a multiply-high by floor((2^32 - 1) / n) + 1: exact
+  // for the numerators here, all below 2^20, since 4 <= n <= 64 on this path)
+  const uint32_t n_magic = 0xffffffffu / (uint32_t)n + 1u;
+  auto div_n = [&](int a) { return (int)__umulhi((uint32_t)a, n_magic); };
   auto make_pre_g = [&](int k, float* dst) {
-    const int hi0 = (k * kPmKC) / n;
-    const int nrow = (k * kPmKC + kPmKC - 1) / n - hi0 + 1;
+    const int hi0 = div_n(k * kPmKC);
+    const int nrow = div_n(k * kPmKC + kPmKC - 1) - hi0 + 1;
     const int r = __builtin_amdgcn_readfirstlane(t / TN);
     const int i = t % TN;
     if (r < nrow) {
@@ -926,12 +930,12 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
       if (hi * n >= M) hi = 0;   // past the last column: never referenced
       float v = 1.0f;
       if constexpr (P > 1) {
-        const int q = hi / n;
+        const int q = div_n(hi);
         if (q != mp_q) {
           mp_q = q;
           mp_pre2 = pre_prod(hi, i, P - 2);
         }
-        v = mp_pre2 * Tf[((P - 2) * n + hi % n) * TN + i];
+        v = mp_pre2 * Tf[((P - 2) * n + (hi - q * n)) * TN + i];
       }
       dst[r * TN + i] = v;
     }
