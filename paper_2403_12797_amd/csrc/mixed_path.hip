@@ -917,9 +917,10 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   int mp_q = -1;
   float mp_pre2 = 1.0f;
   // (divisions by n as a multiply-high by floor((2^32 - 1) / n) + 1: exact
-  // for the numerators here, all below 2^20, since 4 <= n <= 64 on this path)
-  const uint32_t n_magic = 0xffffffffu / (uint32_t)n + 1u;
-  auto div_n = [&](int a) { return (int)__umulhi((uint32_t)a, n_magic); };
+  // for the numerators here, all below 2^20, since n <= 64; n = 1 divides
+  // trivially)
+  const uint32_t n_magic = n > 1 ? 0xffffffffu / (uint32_t)n + 1u : 0u;
+  auto div_n = [&](int a) { return n > 1 ? (int)__umulhi((uint32_t)a, n_magic) : a; };
   auto make_pre_g = [&](int k, float* dst) {
     const int hi0 = div_n(k * kPmKC);
     const int nrow = div_n(k * kPmKC + kPmKC - 1) - hi0 + 1;
@@ -947,8 +948,8 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
       make_pre_g(k, dst);
       return;
     }
-    const int hi0 = (k * kPmKC) / n;
-    const int nrow = (k * kPmKC + kPmKC - 1) / n - hi0 + 1;
+    const int hi0 = div_n(k * kPmKC);
+    const int nrow = div_n(k * kPmKC + kPmKC - 1) - hi0 + 1;
     for (int u = t; u < nrow * TN; u += kPmThreads) {
       const int r = __builtin_amdgcn_readfirstlane(u / TN);
       const int i = u % TN;
@@ -1086,6 +1087,11 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
       for (int cb = 0; cb < C::CB; ++cb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[a][cb][r] = 0.0f;
+    float vs[2][16];     // per lane: running sums of squares of its column over the row blocks
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) vs[a][r] = 0.0f;
     int b = 0, pb = 1;   // stage buffer of the current stage; prefix buffer of the next
     // One stage: MFMAs on stage s0 (buffer b), Phi_* of s1 generated into
     // buffer b^1 with the L^-1 slab of s1 (from R, which is then refilled with
@@ -1130,7 +1136,8 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
       }
       if (pre_next) make_pre(s2.k, pdst);
       if (s0.k == s0.ns - 1) {
-        // squares of this column block, summed over the wave's columns
+        // squares of this column block, summed over the lane's column
+        // blocks into its running FP32 sums (16 row blocks at most)
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1138,13 +1145,7 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
             float s2v = 0.0f;
 #pragma unroll
             for (int cb = 0; cb < C::CB; ++cb) s2v = fmaf(acc[a][cb][r], acc[a][cb][r], s2v);
-            double v = (double)s2v;
-            v += __shfl_xor(v, 1);
-            v += __shfl_xor(v, 2);
-            v += __shfl_xor(v, 4);
-            v += __shfl_xor(v, 8);
-            v += __shfl_xor(v, 16);
-            if ((lane & 31) == 0) ssw[wr * TN + wp * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] += v;
+            vs[a][r] += s2v;
           }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -1167,6 +1168,19 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
       stage(la0, la1);
     }
     if (S & 1) stage(lb0, lb1);
+    // per point, the sum over the wave's 32 column lanes, in FP64
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        double v = (double)vs[a][r];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        v += __shfl_xor(v, 16);
+        if ((lane & 31) == 0) ssw[wr * TN + wp * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] += v;
+      }
   }
   __syncthreads();
   if (t < TN && i0 + t < Ns) {
