@@ -209,12 +209,18 @@ def cpu_baseline(P_full, target_s):
 
 
 def gram_source_fingerprint():
-    """sha256 of the Gram kernel section of mixed_path.hip (constants, table
-    kernel, plan, work item and kernels; not the launchers)."""
+    """sha256 of the code of the Gram kernel section of mixed_path.hip
+    (constants, table kernel, plan, work item and kernels; not the launchers),
+    with comment lines, trailing comments and blank lines dropped."""
     src = open(os.path.join(ROOT, "paper_2403_12797_amd", "csrc", "mixed_path.hip")).read()
     a = src.index("// ================================================================ a3 mixed Gram")
     b = src.index("__global__ void reset_counter_kernel")
-    return hashlib.sha256(src[a:b].encode()).hexdigest()
+    code = []
+    for line in src[a:b].splitlines():
+        line = line.split("//", 1)[0].rstrip()
+        if line:
+            code.append(line)
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()
 
 
 def gram_traffic(P, scheme):

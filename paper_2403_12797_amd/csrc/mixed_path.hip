@@ -163,8 +163,8 @@ __device__ __forceinline__ int gm_row_exp(unsigned maxbits, bool last) {
 // leading p-1 factors.  Per stage the work-group forms PRE once per column
 // prefix it needs, then every thread generates 8 samples of one I-block
 // column and 4 samples of one J-half column with one multiply each, splits
-// them into three BF16 terms and stores them in LDS as
-// [term][column slot][16 samples] (slot pitch padded against bank
+// them into the scheme's terms (two FP16 or three BF16) and stores them in
+// LDS as [term][column slot][16 samples] (slot pitch padded against bank
 // conflicts).  Pipeline (one barrier per stage): while the MFMAs of stage t
 // run, the work-group generates stage t+1, forms PRE of stage t+2 and
 // streams the 1-D tables of stage t+3 from memory.
