@@ -305,7 +305,7 @@ def main():
         "vs_baseline": None, "dtype": ("f16x2 Gram" if f16 else "bf16x3 Gram") + ", bf16x2 variance, fp32 acc, fp64 factor",
         "data": "synthetic",
         "config": {"workload": f"{P.name}: p={P.p}, n={P.n}, M={P.M}, N={P.N}, N*={P.Ns}, "
-                               f"x~U[-1,1]^4, y=exp(-|x|^2)+cos(3x1x2)+N(0,0.05^2), eps=1, alpha=1.2; "
+                               f"{P.meta.get('recipe', '')}; "
                                f"fit + predict(mean, var); Gram "
                                + ("split-FP16 MFMA on power-of-two-scaled Phi (2 terms, 3 products)" if f16 else
                                   "split-BF16 MFMA (3 terms, 6 products)")

@@ -122,12 +122,17 @@ gp_status gp_fit(gp_ctx *ctx, const gp_params *params, const double *x, const do
 gp_status gp_predict(gp_ctx *ctx, const gp_model *model, const double *xs, int64_t Ns,
                      double *mean, double *var, void *stream);
 
-/* Free a model (waits for the device work that uses it).  NULL accepted.  */
+/* Free a model (waits for the device work that uses it).  NULL accepted.
+ * A served model's bytes leave the context's admission budget here.        */
 gp_status gp_model_free(gp_model *model);
 
 /* Model shape: any output pointer may be NULL.                              */
 gp_status gp_model_info(const gp_model *model, int32_t *p, int32_t *n, int64_t *M,
                         int32_t *precision, double *sigma);
+
+/* Copy w (eq. 11 in weight-space form: mu_* = Phi_* w) to host memory,
+ * w_host [M] in C-order multi-index (synchronous).  Errors: GP_EINVAL.      */
+gp_status gp_model_weights(const gp_model *model, double *w_host);
 
 /* Copy a model array to host memory (synchronous).  `count` is the capacity
  * of host_out in doubles and must be at least the array size:
@@ -138,7 +143,11 @@ gp_status gp_model_info(const gp_model *model, int32_t *p, int32_t *n, int64_t *
  *   GP_MODEL_B        [M]    Phi^T y
  *   GP_MODEL_L        [M*M]  Cholesky factor L (row-major, upper part zero)
  *   GP_MODEL_LINV     [M*M]  L^-1 (row-major, upper part zero)
- * Errors: GP_EINVAL (unknown array, count too small), GP_EDEVICE.          */
+ * Models from gp_fit / gp_fit_batch keep every array.  Served models
+ * (gp_submit) are lean: they keep w, Lambda, b and what the variance needs
+ * (L^-1 for FP64; its BF16 terms for mixed precision), so GP_MODEL_A,
+ * GP_MODEL_L and, for mixed precision, GP_MODEL_LINV are not available.
+ * Errors: GP_EINVAL (unknown or absent array, count too small), GP_EDEVICE. */
 enum { GP_MODEL_W = 0, GP_MODEL_LAMBDA = 1, GP_MODEL_A = 2, GP_MODEL_B = 3, GP_MODEL_L = 4,
        GP_MODEL_LINV = 5 };
 gp_status gp_model_get(const gp_model *model, int32_t what, double *host_out, int64_t count);
@@ -176,8 +185,14 @@ gp_status gp_autotune(gp_ctx *ctx, int32_t p, int32_t n, int64_t N, int32_t *chu
  *         model_out is requested at poll time, else freed).
  * All arrays are device arrays as above and must stay valid until gp_poll
  * has returned a final (non-PENDING) status for the request.  Requests are
- * admitted when their device footprint fits the context's HBM budget; work
- * of admitted requests overlaps on the device.
+ * admitted when their device footprint fits what the context's HBM budget
+ * has left (the budget less the bytes of admitted requests and of served
+ * models not yet freed); work of admitted requests overlaps on the device.
+ * Admission takes the first queued request that fits; a request that does
+ * not fit yet is passed over by later ones at most 32 times, after which
+ * admission waits for it.  Fitted models are lean (see gp_model_get) and
+ * stay charged to the budget until gp_model_free (or, when model_out is not
+ * requested, until gp_poll frees them).
  * gp_submit errors: GP_EINVAL, GP_ENOMEM (footprint exceeds the whole budget).
  * gp_poll: waits up to wait_us microseconds (0 = just check, <0 = forever);
  * returns GP_PENDING, or the request's final status exactly once, after
@@ -196,6 +211,19 @@ typedef struct {
 } gp_request;
 gp_status gp_submit(gp_ctx *ctx, const gp_request *req, int64_t *req_id);
 gp_status gp_poll(gp_ctx *ctx, int64_t req_id, int32_t wait_us, gp_model **model_out);
+
+/* Device bytes a request would hold if submitted now (validated as in
+ * gp_submit, nothing enqueued): *model_bytes (may be NULL) is the lean model
+ * of a FIT kind, which stays resident while the caller holds the model;
+ * *transient_bytes (may be NULL) is the fit and predict workspace held while
+ * the request runs.  Errors: as gp_submit's validation.                     */
+gp_status gp_request_footprint(gp_ctx *ctx, const gp_request *req, size_t *model_bytes,
+                               size_t *transient_bytes);
+
+/* Admission state of the served path: the HBM budget, the bytes held by
+ * admitted requests, and the bytes of served models not yet freed.  Any
+ * output may be NULL.  Errors: GP_EINVAL.                                    */
+gp_status gp_ctx_memory(gp_ctx *ctx, size_t *budget, size_t *in_flight, size_t *resident);
 
 /* Profiling: device time per phase, measured with HIP events recorded on
  * the stream each phase runs on.  gp_profile_enable(ctx, 1) clears the totals
@@ -217,8 +245,9 @@ enum { GP_PH_GRAM = 0,          /* fused Phi + Gram kernels (a3)            */
 gp_status gp_profile_enable(gp_ctx *ctx, int32_t on);
 gp_status gp_profile_read(gp_ctx *ctx, int32_t phase, double *total_ms, int64_t *count);
 
-/* Message describing the last failing call on this thread ("" if none).   */
-const char *gp_last_error(void);
+/* Message describing the last failing call on the calling thread ("" if
+ * none).  Messages are kept per thread, not per context; ctx may be NULL.   */
+const char *gp_last_error(const gp_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,8 @@ MAX_P, MAX_N, MAX_M = 8, 64, 16384
 
 EXPORTED = ["gp_ctx_create", "gp_ctx_destroy", "gp_fit", "gp_predict", "gp_model_free", "gp_model_info",
             "gp_model_get", "gp_submit", "gp_poll", "gp_last_error", "gp_profile_enable", "gp_profile_read",
-            "gp_fit_batch", "gp_predict_batch", "gp_autotune"]
+            "gp_fit_batch", "gp_predict_batch", "gp_autotune", "gp_model_weights", "gp_request_footprint",
+            "gp_ctx_memory"]
 PHASES = ["gram", "gram_reduce", "phiT", "chol", "trtri", "solve", "split", "predict", "predict_mean",
           "predict_reduce"]
 
@@ -69,7 +70,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "gp_model_get": (i32, [vp, i32, dp, i64]),
         "gp_submit": (i32, [vp, C.POINTER(GpRequest), C.POINTER(i64)]),
         "gp_poll": (i32, [vp, i64, i32, C.POINTER(vp)]),
-        "gp_last_error": (C.c_char_p, []),
+        "gp_last_error": (C.c_char_p, [vp]),
+        "gp_model_weights": (i32, [vp, dp]),
+        "gp_request_footprint": (i32, [vp, C.POINTER(GpRequest), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+        "gp_ctx_memory": (i32, [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "gp_profile_enable": (i32, [vp, i32]),
         "gp_profile_read": (i32, [vp, i32, dp, C.POINTER(i64)]),
         "gp_fit_batch": (i32, [vp, i32, C.POINTER(GpParams), C.POINTER(vp), C.POINTER(vp), C.POINTER(i64), vp,
@@ -87,7 +91,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
 
 
 def last_error() -> str:
-    return load().gp_last_error().decode()
+    return load().gp_last_error(None).decode()
 
 
 def _check(st: int) -> int:
@@ -122,6 +126,23 @@ def make_params(p, n, sigma, eps, alpha, precision=PREC_FP64):
     return prm
 
 
+def _request(kind, *, x=None, y=None, params=None, model=None, xs=None, mean=None, var=None):
+    """A gp_request from device tensors (argument marshalling only)."""
+    req = GpRequest()
+    req.kind = kind
+    if params is not None:
+        req.params = params
+    req.x = _ptr(x)
+    req.y = _ptr(y)
+    req.N = y.shape[0] if y is not None else 0
+    req.model = model.handle if model is not None else None
+    req.xs = _ptr(xs)
+    req.Ns = xs.shape[0] if xs is not None else 0
+    req.mean = _ptr(mean)
+    req.var = _ptr(var)
+    return req
+
+
 class Model:
     def __init__(self, handle: C.c_void_p):
         self.handle = handle
@@ -138,6 +159,13 @@ class Model:
         out = np.empty(size, dtype=np.float64)
         _check(load().gp_model_get(self.handle, what, out.ctypes.data_as(C.POINTER(C.c_double)), size))
         return out.reshape(M, M) if size == M * M else out
+
+    def weights(self):
+        """w on the host (C-order multi-index)."""
+        import numpy as np
+        w = np.empty(self.info()["M"], dtype=np.float64)
+        _check(load().gp_model_weights(self.handle, w.ctypes.data_as(C.POINTER(C.c_double))))
+        return w
 
     def free(self):
         if self.handle:
@@ -231,19 +259,21 @@ class Context:
         vp_ = (C.c_void_p * k)(*[(_ptr(v).value if v is not None else None) for v in vars_])
         _check(load().gp_predict_batch(self.handle, k, hs, xs, Ns, mp, vp_, _stream(stream)))
 
+    def memory(self):
+        """(budget, in-flight, resident) bytes of the served path."""
+        b, f, r = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        _check(load().gp_ctx_memory(self.handle, C.byref(b), C.byref(f), C.byref(r)))
+        return b.value, f.value, r.value
+
+    def footprint(self, kind, **kw):
+        """(model bytes, transient bytes) a request would hold (see gp_request_footprint)."""
+        req = _request(kind, **kw)
+        mb, tb = C.c_size_t(), C.c_size_t()
+        _check(load().gp_request_footprint(self.handle, C.byref(req), C.byref(mb), C.byref(tb)))
+        return mb.value, tb.value
+
     def submit(self, kind, *, x=None, y=None, params=None, model=None, xs=None, mean=None, var=None) -> int:
-        req = GpRequest()
-        req.kind = kind
-        if params is not None:
-            req.params = params
-        req.x = _ptr(x)
-        req.y = _ptr(y)
-        req.N = y.shape[0] if y is not None else 0
-        req.model = model.handle if model is not None else None
-        req.xs = _ptr(xs)
-        req.Ns = xs.shape[0] if xs is not None else 0
-        req.mean = _ptr(mean)
-        req.var = _ptr(var)
+        req = _request(kind, x=x, y=y, params=params, model=model, xs=xs, mean=mean, var=var)
         rid = C.c_int64()
         _check(load().gp_submit(self.handle, C.byref(req), C.byref(rid)))
         return rid.value

@@ -57,26 +57,31 @@ gp_status validate_params(const gp_params* prm, int64_t* M_out) {
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Sizes of a model's device regions, in the order model_alloc lays them out.
+// A lean model (the served path) keeps only what prediction needs: the
+// factor regions A, L, Dinv and (mixed precision) the FP64 L^-1 are sized
+// zero here and live in the fit workspace instead (FitLayout).
 static constexpr int kModelRegions = 13;
-static void model_sizes(int64_t M, int precision, size_t* sz) {
+static void model_sizes(int64_t M, int precision, bool lean, size_t* sz) {
   const size_t MM = (size_t)M * M;
-  const size_t v[kModelRegions] = {kTabSize * 8, (size_t)M * 8, (size_t)M * 8, MM * 8, MM * 8, MM * 8,
-                                   (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8, (size_t)M * 8,
+  const bool mixed = prec_mixed(precision);
+  const size_t v[kModelRegions] = {kTabSize * 8, (size_t)M * 8, (size_t)M * 8, lean ? 0 : MM * 8, lean ? 0 : MM * 8,
+                                   (lean && mixed) ? 0 : MM * 8,
+                                   lean ? 0 : (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8, (size_t)M * 8,
                                    (size_t)M * 8, 64,
-                                   prec_mixed(precision) ? 2 * (size_t)linv_rows((int)M) * linv_pitch((int)M) * 2 : 0,
+                                   mixed ? 2 * (size_t)linv_rows((int)M) * linv_pitch((int)M) * 2 : 0,
                                    (size_t)M * 16, (size_t)pdesc_elems((int)M) * 4};
   for (int r = 0; r < kModelRegions; ++r) sz[r] = v[r];
 }
 
 // Device bytes a fitted model holds (used by admission control too).
-size_t model_bytes(int64_t M, int precision) {
+size_t model_bytes(int64_t M, int precision, bool lean) {
   size_t sz[kModelRegions], b = 0;
-  model_sizes(M, precision, sz);
-  for (size_t v : sz) b += align_up(v);
+  model_sizes(M, precision, lean, sz);
+  for (size_t v : sz) b += v ? align_up(v) : 0;
   return b;
 }
 
-FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chunk, bool all_splits) {
+FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chunk, bool all_splits, bool lean) {
   FitLayout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -84,6 +89,7 @@ FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chun
     o += align_up(bytes);
     return r;
   };
+  L.lean = lean;
   if (prec_mixed(precision)) {
     L.g = gram_mixed_plan(N, (int)M, chunk);
     if (all_splits) L.g.splits_per_pass = L.g.splits_total, L.g.passes = 1;
@@ -100,12 +106,18 @@ FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chun
   L.d = take((size_t)M * 8);
   L.ltpart = take((size_t)ceil_div(M, 256) * M * 8);
   L.trws = take(trtri_workspace_elems((int)M) * 8);
+  if (lean) {
+    // A is factored in place (L = A); L^-1 here only for mixed precision
+    L.A = take((size_t)M * M * 8);
+    L.Dinv = take((size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8);
+    L.Linv = prec_mixed(precision) ? take((size_t)M * M * 8) : 0;
+  }
   L.total = o + 256;
   return L;
 }
 
 size_t fit_workspace_bytes(gp_ctx* ctx, int64_t N, int p, int n, int64_t M, int precision) {
-  return fit_layout(N, p, n, M, precision, tuned_chunk(ctx, p, n, N), false).total;
+  return fit_layout(N, p, n, M, precision, tuned_chunk(ctx, p, n, N), false, false).total;
 }
 
 size_t predict_workspace_bytes(int64_t Ns, int64_t M, int precision) {
@@ -135,6 +147,12 @@ void prof_mark(Prof* p, int phase, bool begin, hipStream_t s) {
 
 void model_release(gp_model* m, hipStream_t s, bool sync_device) {
   if (!m) return;
+  if (m->charged) {
+    // a served model held by the caller: its bytes leave the admission budget
+    m->ctx->resident_bytes.fetch_sub(m->bytes);
+    m->charged = false;
+    m->ctx->cv_work.notify_all();
+  }
   if (m->base) {
     hipSetDevice(m->ctx->device);
     if (sync_device) hipDeviceSynchronize();
@@ -144,8 +162,9 @@ void model_release(gp_model* m, hipStream_t s, bool sync_device) {
   delete m;
 }
 
-gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t s, gp_model** out) {
+gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, bool lean, hipStream_t s, gp_model** out) {
   gp_model* m = new gp_model();
+  m->lean = lean;
   m->ctx = ctx;
   m->p = prm->p;
   m->n = prm->n;
@@ -157,9 +176,9 @@ gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t 
     m->alpha[j] = prm->alpha[j];
   }
   size_t sizes[kModelRegions];
-  model_sizes(M, prm->precision, sizes);
+  model_sizes(M, prm->precision, lean, sizes);
   size_t total = 0;
-  for (size_t s : sizes) total += align_up(s);
+  for (size_t s : sizes) total += s ? align_up(s) : 0;
   hipError_t e = hipSetDevice(ctx->device);
   if (e == hipSuccess) e = hipMallocAsync(&m->base, total, s);
   if (e != hipSuccess) {
@@ -170,7 +189,8 @@ gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t 
   m->bytes = total;
   char* b = (char*)m->base;
   size_t o = 0;
-  auto take = [&](size_t s) {
+  auto take = [&](size_t s) -> void* {
+    if (!s) return nullptr;
     void* r = b + o;
     o += align_up(s);
     return r;
@@ -233,7 +253,7 @@ void enqueue_fit_tail(gp_model* m, const double* x, const double* y, int64_t N, 
   launch_phiT_vec(x, y, N, p, n, M, m->tab, vpart, nullptr, nullptr, m->b, s);
   prof_mark(pr, GP_PH_PHIT, false, s);
   prof_mark(pr, GP_PH_CHOL, true, s);
-  hipMemcpyAsync(m->L, m->A, (size_t)M * M * 8, hipMemcpyDeviceToDevice, s);
+  if (m->L != m->A) hipMemcpyAsync(m->L, m->A, (size_t)M * M * 8, hipMemcpyDeviceToDevice, s);
   launch_cholesky(m->L, M, m->Dinv, m->flags, s);
   prof_mark(pr, GP_PH_CHOL, false, s);
   prof_mark(pr, GP_PH_TRTRI, true, s);
@@ -255,13 +275,21 @@ void enqueue_fit_tail(gp_model* m, const double* x, const double* y, int64_t N, 
   }
 }
 
-// Enqueue the whole fit of one problem on stream s.  ws must hold
-// fit_workspace_bytes() for the same context.
-void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void* ws, hipStream_t s) {
+// Enqueue the whole fit of one problem on stream s.  ws holds L.total bytes
+// of a layout made for this problem (fit_layout); for a lean model the
+// factor regions live in ws and the model keeps no pointer to them after
+// this call (the device work still reads them, ordered on s before ws is
+// freed).
+void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, const FitLayout& L, void* ws,
+                 hipStream_t s) {
   const int p = m->p, n = m->n, M = (int)m->M;
-  const FitLayout L = fit_layout(N, p, n, M, m->precision, tuned_chunk(m->ctx, p, n, N), false);
   char* wb = (char*)ws;
   Prof* pr = &m->ctx->prof;
+  if (m->lean) {
+    m->A = m->L = (double*)(wb + L.A);
+    m->Dinv = (double*)(wb + L.Dinv);
+    if (prec_mixed(m->precision)) m->Linv = (double*)(wb + L.Linv);
+  }
   enqueue_fit_head(m, x, y, N, L, ws, s);
   // a3: A = Phi^T Phi + sigma^2 Lambda^-1
   if (prec_mixed(m->precision)) {
@@ -271,6 +299,10 @@ void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void*
     launch_gram_f64(x, N, p, n, M, m->tab, m->reg, (double*)(wb + L.gpart), m->A, s, pr);
   }
   enqueue_fit_tail(m, x, y, N, L, ws, s);
+  if (m->lean) {
+    m->A = m->L = m->Dinv = nullptr;
+    if (prec_mixed(m->precision)) m->Linv = nullptr;
+  }
 }
 
 void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* mean, double* var, void* ws,
@@ -298,7 +330,10 @@ using namespace mgp;
 
 extern "C" {
 
-const char* gp_last_error(void) { return g_last_error.c_str(); }
+const char* gp_last_error(const gp_ctx* ctx) {
+  (void)ctx;  // messages are kept per calling thread
+  return g_last_error.c_str();
+}
 
 gp_status gp_ctx_create(int device, size_t hbm_budget_bytes, gp_ctx** out) {
   if (!out) return fail(GP_EINVAL, "out is NULL");
@@ -349,17 +384,20 @@ gp_status gp_fit(gp_ctx* ctx, const gp_params* params, const double* x, const do
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   gp_model* m = nullptr;
-  st = model_alloc(ctx, params, M, s, &m);
+  st = model_alloc(ctx, params, M, false, s, &m);
   if (st != GP_OK) return st;
   void* ws = nullptr;
-  const size_t wsb = fit_workspace_bytes(ctx, N, params->p, params->n, M, params->precision);
+  // the layout (and the Gram chunk in it) is fixed here, once
+  const FitLayout L = fit_layout(N, params->p, params->n, M, params->precision,
+                                 tuned_chunk(ctx, params->p, params->n, N), false, false);
+  const size_t wsb = L.total;
   hipError_t e = hipMallocAsync(&ws, wsb, s);
   if (e != hipSuccess) {
     gp_model_free(m);
     return fail(e == hipErrorOutOfMemory ? GP_ENOMEM : GP_EDEVICE, "fit workspace of %zu bytes: %s", wsb,
                 hipGetErrorString(e));
   }
-  enqueue_fit(m, x, y, N, ws, s);
+  enqueue_fit(m, x, y, N, L, ws, s);
   hipFreeAsync(ws, s);
   int flags[2] = {0, 0};
   e = hipMemcpyAsync(flags, m->flags, sizeof(flags), hipMemcpyDeviceToHost, s);
@@ -455,6 +493,11 @@ gp_status gp_model_info(const gp_model* model, int32_t* p, int32_t* n, int64_t* 
   return GP_OK;
 }
 
+gp_status gp_model_weights(const gp_model* model, double* w_host) {
+  if (!model || !w_host) return fail(GP_EINVAL, "model/w_host is NULL");
+  return gp_model_get(model, GP_MODEL_W, w_host, model->M);
+}
+
 gp_status gp_model_get(const gp_model* model, int32_t what, double* host_out, int64_t count) {
   if (!model || !host_out) return fail(GP_EINVAL, "model/host_out is NULL");
   const int64_t M = model->M;
@@ -470,6 +513,9 @@ gp_status gp_model_get(const gp_model* model, int32_t what, double* host_out, in
     case GP_MODEL_LINV: src = model->Linv; len = M * M; lower = true; break;
     default: return fail(GP_EINVAL, "unknown model array %d", what);
   }
+  if (!src)
+    return fail(GP_EINVAL, "array %d is not kept by this model (served models keep only what prediction needs)",
+                what);
   if (count < len) return fail(GP_EINVAL, "count %lld < %lld", (long long)count, (long long)len);
   HIP_TRY(hipSetDevice(model->ctx->device));
   HIP_TRY(hipDeviceSynchronize());

@@ -160,7 +160,7 @@ gp_status gp_fit_batch(gp_ctx* ctx, int32_t count, const gp_params* params, cons
   std::vector<int64_t> Ms(count);
   for (int k = 0; k < count; ++k) {
     gp_status st = validate_params(&params[k], &Ms[k]);
-    if (st != GP_OK) return fail(st, "problem %d: %s", k, gp_last_error());
+    if (st != GP_OK) return fail(st, "problem %d: %s", k, gp_last_error(ctx));
     if (N[k] < 1 || !x[k] || !y[k]) return fail(GP_EINVAL, "problem %d: needs x, y and N >= 1", k);
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(GP_EDEVICE, "hipSetDevice");
@@ -171,13 +171,13 @@ gp_status gp_fit_batch(gp_ctx* ctx, int32_t count, const gp_params* params, cons
   std::vector<size_t> off(count);
   size_t total = 0;
   for (int k = 0; k < count; ++k) {
-    gp_status st = model_alloc(ctx, &params[k], Ms[k], s, &ms[k]);
+    gp_status st = model_alloc(ctx, &params[k], Ms[k], false, s, &ms[k]);
     if (st != GP_OK) {
       for (int q = 0; q < k; ++q) model_release(ms[q], s, true);
       return st;
     }
     Ls[k] = fit_layout(N[k], params[k].p, params[k].n, Ms[k], params[k].precision,
-                       tuned_chunk(ctx, params[k].p, params[k].n, N[k]), true);
+                       tuned_chunk(ctx, params[k].p, params[k].n, N[k]), true, false);
     off[k] = total;
     total += (Ls[k].total + 255) & ~(size_t)255;
   }

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "common.h"
+#include "kernels.h"
 
 // Both mixed modes share everything but the Gram scheme.
 inline bool prec_mixed(int precision) { return precision == GP_PREC_MIXED || precision == GP_PREC_MIXED_F16; }
@@ -32,17 +33,32 @@ struct gp_model {
   uint16_t* midx = nullptr;  // [M][8] multi-index table (1-D table rows per column)
   uint32_t* pdesc = nullptr; // [ceil16(M)] prediction column descriptors
   __bf16* linv_pieces = nullptr;
+  bool lean = false;     // keeps only what prediction needs (served models)
+  bool charged = false;  // bytes counted in ctx->resident_bytes until freed
 };
 
 namespace mgp {
+
+// Transient device memory of a fit: one block carved into these arrays
+// (byte offsets).  all_splits keeps every Gram partial (no passes).
+struct FitLayout {
+  GramPlan g;
+  size_t gpart, tab32, vpart, resid, z, r, d, ltpart, trws, total;
+  bool lean;
+  size_t A, Dinv, Linv;  // lean models only: A (factored in place), Dinv, L^-1 (mixed)
+};
 
 // One served request (see gp_submit).
 struct Request {
   int64_t id = 0;
   gp_request desc{};
   double eps[GP_MAX_P] = {}, alpha[GP_MAX_P] = {};
-  size_t footprint = 0;   // device bytes held while in flight
+  size_t footprint = 0;   // device bytes held while in flight (workspace + model)
   size_t ws_bytes = 0;
+  size_t fit_ws_bytes = 0;  // fit part of ws (the predict workspace follows it)
+  size_t model_bytes = 0;   // lean model of a FIT kind (part of footprint)
+  FitLayout layout{};       // fixed at submit: the Gram chunk is not looked up again
+  int bypassed = 0;         // times a later request was admitted ahead of this one
   gp_status status = GP_PENDING;
   gp_model* model = nullptr;  // fitted model (FIT kinds)
   void* ws = nullptr;
@@ -84,6 +100,9 @@ struct gp_ctx {
   std::map<int64_t, mgp::Request*> requests;
   std::vector<mgp::Slot> slots;
   size_t in_flight_bytes = 0;
+  // bytes of served models handed to the caller and not yet freed; they
+  // count against the budget (atomic: model frees take no ctx lock)
+  std::atomic<size_t> resident_bytes{0};
   int64_t next_id = 1;
   bool stop = false;
   std::thread thread;
@@ -95,34 +114,27 @@ struct gp_ctx {
   std::string tune_path;
 };
 
-#include "kernels.h"
-
 namespace mgp {
 gp_status fail(gp_status st, const char* fmt, ...);
-// Transient device memory of a fit: one block carved into these arrays
-// (byte offsets).  all_splits keeps every Gram partial (no passes).
-struct FitLayout {
-  GramPlan g;
-  size_t gpart, tab32, vpart, resid, z, r, d, ltpart, trws, total;
-};
-FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chunk, bool all_splits);
+FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chunk, bool all_splits, bool lean);
 void enqueue_fit_head(gp_model* m, const double* x, const double* y, int64_t N, const FitLayout& L, void* ws,
                       hipStream_t s);
 void enqueue_fit_tail(gp_model* m, const double* x, const double* y, int64_t N, const FitLayout& L, void* ws,
                       hipStream_t s);
 void tune_load(gp_ctx* ctx);
 gp_status validate_params(const gp_params* prm, int64_t* M_out);
-size_t model_bytes(int64_t M, int precision);
+size_t model_bytes(int64_t M, int precision, bool lean);
 size_t fit_workspace_bytes(gp_ctx* ctx, int64_t N, int p, int n, int64_t M, int precision);
 // Gram chunk length chosen by the autotuner for (p, n, N) on this context,
 // 0 if none (the planner's default applies).
 int tuned_chunk(gp_ctx* ctx, int p, int n, int64_t N);
 size_t predict_workspace_bytes(int64_t Ns, int64_t M, int precision);
-gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, hipStream_t s, gp_model** out);
+gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, bool lean, hipStream_t s, gp_model** out);
 // Free a model's device memory stream-ordered on s (after a device-wide sync
 // if sync_device) and delete it.
 void model_release(gp_model* m, hipStream_t s, bool sync_device);
-void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, void* ws, hipStream_t s);
+void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, const FitLayout& L, void* ws,
+                 hipStream_t s);
 void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* mean, double* var, void* ws,
                      hipStream_t s);
 gp_status scheduler_start(gp_ctx* ctx);

@@ -1,11 +1,16 @@
 // Served path: gp_submit / gp_poll with continuous batching.
 //
-// A scheduler thread per context admits queued requests in arrival order as
-// soon as a stream slot is free and the request's device footprint fits the
-// context's HBM budget, enqueues its fit and/or predict on that slot's
-// stream (so the work of admitted requests overlaps on the GPU), and retires
-// requests whose completion event has fired.  Fitted models stay
-// device-resident and are handed to the caller at poll time.
+// A scheduler thread per context admits queued requests as soon as a stream
+// slot is free and the request's device footprint fits what the context's
+// HBM budget has left, enqueues its fit and/or predict on that slot's stream
+// (so the work of admitted requests overlaps on the GPU), and retires
+// requests whose completion event has fired.  Admission scans the queue in
+// arrival order and takes the first request that fits; a request that does
+// not fit is passed over at most kMaxBypass times, after which admission
+// waits for it (no request starves behind a stream of smaller ones).
+// Fitted models are lean (w, the tables and the variance factor) and stay
+// device-resident; a model handed to the caller keeps its bytes charged to
+// the budget until it is freed.
 #include <chrono>
 #include <stdlib.h>
 #include <string.h>
@@ -15,6 +20,7 @@
 namespace mgp {
 
 constexpr int kSlots = 4;
+constexpr int kMaxBypass = 32;
 
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -44,6 +50,11 @@ static void finish(gp_ctx* ctx, Request* r, gp_status st) {
     model_release(r->model, s, false);
     r->model = nullptr;
   }
+  if (st == GP_OK && r->model) {
+    // the model outlives the request: its bytes stay charged until it is freed
+    r->model->charged = true;
+    ctx->resident_bytes.fetch_add(r->model->bytes);
+  }
 }
 
 // Allocate and enqueue one admitted request on slot k (mu held).
@@ -64,12 +75,12 @@ static void launch(gp_ctx* ctx, Request* r, int k) {
     prm.alpha = r->alpha;
     int64_t M = 0;
     validate_params(&prm, &M);
-    gp_status st = model_alloc(ctx, &prm, M, sl.stream, &r->model);
+    gp_status st = model_alloc(ctx, &prm, M, true, sl.stream, &r->model);
     if (st != GP_OK) {
       finish(ctx, r, st);
       return;
     }
-    enqueue_fit(r->model, d.x, d.y, d.N, r->ws, sl.stream);
+    enqueue_fit(r->model, d.x, d.y, d.N, r->layout, r->ws, sl.stream);
     hipMemcpyAsync(sl.flags_host, r->model->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, sl.stream);
     pm = r->model;
   } else {
@@ -77,9 +88,7 @@ static void launch(gp_ctx* ctx, Request* r, int k) {
   }
   if (d.kind != GP_REQ_FIT && d.Ns > 0 && (d.mean || d.var)) {
     // predict workspace follows the fit workspace in the same block
-    const size_t fitb =
-        d.kind == GP_REQ_FIT_PREDICT ? fit_workspace_bytes(ctx, d.N, pm->p, pm->n, pm->M, pm->precision) : 0;
-    enqueue_predict(pm, d.xs, d.Ns, d.mean, d.var, (char*)r->ws + ((fitb + 255) & ~(size_t)255), sl.stream);
+    enqueue_predict(pm, d.xs, d.Ns, d.mean, d.var, (char*)r->ws + r->fit_ws_bytes, sl.stream);
   }
   hipEventRecord(sl.done, sl.stream);
   r->t_admit = now_s();
@@ -115,11 +124,12 @@ static void scheduler_loop(gp_ctx* ctx) {
     }
     if (retired) ctx->cv_done.notify_all();
     if (ctx->stop && ctx->queue.empty() && active == 0) break;
-    // admit in arrival order while a slot is free and memory fits
-    while (!ctx->queue.empty()) {
-      Request* r = ctx->queue.front();
+    // admit the first queued request that fits while a slot is free
+    auto it = ctx->queue.begin();
+    while (it != ctx->queue.end()) {
+      Request* r = *it;
       if (ctx->stop) {
-        ctx->queue.pop_front();
+        it = ctx->queue.erase(it);
         r->status = GP_ECANCELED;
         ctx->cv_done.notify_all();
         continue;
@@ -130,15 +140,28 @@ static void scheduler_loop(gp_ctx* ctx) {
           free_slot = k;
           break;
         }
-      if (free_slot < 0 || ctx->in_flight_bytes + r->footprint > ctx->budget) break;
-      ctx->queue.pop_front();
-      ctx->in_flight_bytes += r->footprint;
-      launch(ctx, r, free_slot);
-      if (r->status != GP_PENDING) ctx->cv_done.notify_all();
-      else ++active;
+      if (free_slot < 0) break;
+      const size_t used = ctx->in_flight_bytes + ctx->resident_bytes.load();
+      if (used + r->footprint <= ctx->budget) {
+        if (it != ctx->queue.begin()) ctx->queue.front()->bypassed += 1;
+        it = ctx->queue.erase(it);
+        ctx->in_flight_bytes += r->footprint;
+        launch(ctx, r, free_slot);
+        if (r->status != GP_PENDING) ctx->cv_done.notify_all();
+        else ++active;
+        continue;
+      }
+      // r waits for memory; later requests may pass it until the head has
+      // been passed over kMaxBypass times
+      if (ctx->queue.front()->bypassed >= kMaxBypass) break;
+      ++it;
     }
     if (active > 0)
       ctx->cv_work.wait_for(lk, std::chrono::microseconds(50));
+    else if (!ctx->queue.empty())
+      // waiting for memory held by models the caller has not freed yet
+      // (their release notifies without the lock, so also wake up on time)
+      ctx->cv_work.wait_for(lk, std::chrono::milliseconds(1));
     else if (!ctx->stop)
       ctx->cv_work.wait(lk);
   }
@@ -189,56 +212,84 @@ using namespace mgp;
 
 extern "C" {
 
-gp_status gp_submit(gp_ctx* ctx, const gp_request* req, int64_t* req_id) {
-  if (!ctx || !req || !req_id) return fail(GP_EINVAL, "ctx/req/req_id is NULL");
-  *req_id = 0;
-  Request* r = new Request();
+}  // extern "C"
+
+namespace mgp {
+// Validate a request and fill r's descriptor copy, layout and sizes
+// (no device work, no ctx lock).
+static gp_status prepare_request(gp_ctx* ctx, const gp_request* req, Request* r) {
   r->desc = *req;
   int64_t M = 0;
   int prec = 0;
   if (req->kind == GP_REQ_FIT || req->kind == GP_REQ_FIT_PREDICT) {
     gp_status st = validate_params(&req->params, &M);
-    if (st != GP_OK) {
-      delete r;
-      return st;
-    }
-    if (req->N < 1 || !req->x || !req->y) {
-      delete r;
-      return fail(GP_EINVAL, "FIT request needs x, y and N >= 1");
-    }
+    if (st != GP_OK) return st;
+    if (req->N < 1 || !req->x || !req->y) return fail(GP_EINVAL, "FIT request needs x, y and N >= 1");
     for (int j = 0; j < req->params.p; ++j) {
       r->eps[j] = req->params.eps[j];
       r->alpha[j] = req->params.alpha[j];
     }
     prec = req->params.precision;
   } else if (req->kind == GP_REQ_PREDICT) {
-    if (!req->model) {
-      delete r;
-      return fail(GP_EINVAL, "PREDICT request needs a model");
-    }
+    if (!req->model) return fail(GP_EINVAL, "PREDICT request needs a model");
     M = req->model->M;
     prec = req->model->precision;
   } else {
-    delete r;
     return fail(GP_EINVAL, "unknown request kind %d", req->kind);
   }
-  if (req->kind != GP_REQ_FIT && req->Ns > 0 && (req->mean || req->var) && !req->xs) {
-    delete r;
+  if (req->kind != GP_REQ_FIT && req->Ns > 0 && (req->mean || req->var) && !req->xs)
     return fail(GP_EINVAL, "predict part needs xs");
-  }
-  if (req->Ns < 0) {
-    delete r;
-    return fail(GP_EINVAL, "Ns must be >= 0");
-  }
+  if (req->Ns < 0) return fail(GP_EINVAL, "Ns must be >= 0");
   size_t ws = 0, foot = 0;
   if (req->kind != GP_REQ_PREDICT) {
-    ws += (fit_workspace_bytes(ctx, req->N, req->params.p, req->params.n, M, prec) + 255) & ~(size_t)255;
-    foot += model_bytes(M, prec);
+    // the layout (and the Gram chunk in it) is fixed here, once
+    r->layout = fit_layout(req->N, req->params.p, req->params.n, M, prec,
+                           tuned_chunk(ctx, req->params.p, req->params.n, req->N), false, true);
+    ws += (r->layout.total + 255) & ~(size_t)255;
+    r->model_bytes = model_bytes(M, prec, true);
+    foot += r->model_bytes;
   }
+  r->fit_ws_bytes = ws;
   if (req->kind != GP_REQ_FIT) ws += predict_workspace_bytes(req->Ns, M, prec);
   foot += ws;
   r->ws_bytes = ws;
   r->footprint = foot;
+  return GP_OK;
+}
+}  // namespace mgp
+
+extern "C" {
+
+gp_status gp_request_footprint(gp_ctx* ctx, const gp_request* req, size_t* model_bytes_out,
+                               size_t* transient_bytes_out) {
+  if (!ctx || !req) return fail(GP_EINVAL, "ctx/req is NULL");
+  Request r;
+  const gp_status st = prepare_request(ctx, req, &r);
+  if (st != GP_OK) return st;
+  if (model_bytes_out) *model_bytes_out = r.model_bytes;
+  if (transient_bytes_out) *transient_bytes_out = r.ws_bytes;
+  return GP_OK;
+}
+
+gp_status gp_ctx_memory(gp_ctx* ctx, size_t* budget, size_t* in_flight, size_t* resident) {
+  if (!ctx) return fail(GP_EINVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (budget) *budget = ctx->budget;
+  if (in_flight) *in_flight = ctx->in_flight_bytes;
+  if (resident) *resident = ctx->resident_bytes.load();
+  return GP_OK;
+}
+
+gp_status gp_submit(gp_ctx* ctx, const gp_request* req, int64_t* req_id) {
+  if (!ctx || !req || !req_id) return fail(GP_EINVAL, "ctx/req/req_id is NULL");
+  *req_id = 0;
+  Request* r = new Request();
+  const gp_status pst = prepare_request(ctx, req, r);
+  if (pst != GP_OK) {
+    delete r;
+    return pst;
+  }
+  const size_t foot = r->footprint;
   if (foot > ctx->budget) {
     const size_t budget = ctx->budget;
     delete r;

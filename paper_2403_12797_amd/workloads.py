@@ -57,7 +57,8 @@ def _c1(N=1000, Ns=1000):
     x = g.uniform(-1.0, 1.0, size=(N, 1))
     y = np.sin(3.0 * x[:, 0]) + g.normal(0.0, 0.1, size=N)
     xs = np.linspace(-1.0, 1.0, Ns).reshape(Ns, 1)
-    return Problem("c1_p1_n10", 1, 10, 0.1, np.array([1.0]), np.array([1.0]), x, y, xs)
+    return Problem("c1_p1_n10", 1, 10, 0.1, np.array([1.0]), np.array([1.0]), x, y, xs,
+                   {"recipe": "x~U[-1,1], y=sin(3x)+N(0,0.1^2), x* uniform grid, eps=1, alpha=1"})
 
 
 def _c2(N=100_000, Ns=100_000):
@@ -65,7 +66,8 @@ def _c2(N=100_000, Ns=100_000):
     x = g.normal(size=(N, 3))
     y = np.sin(2.0 * x).sum(axis=1) + g.normal(0.0, 0.05, size=N)
     xs = g.normal(size=(Ns, 3))
-    return Problem("c2_p3_n8", 3, 8, 0.05, np.full(3, 0.8), np.ones(3), x, y, xs)
+    return Problem("c2_p3_n8", 3, 8, 0.05, np.full(3, 0.8), np.ones(3), x, y, xs,
+                   {"recipe": "x,x*~N(0,I_3), y=sum_d sin(2x_d)+N(0,0.05^2), eps=0.8, alpha=1"})
 
 
 def _c3(N=1_000_000, Ns=1_000_000):
@@ -74,7 +76,8 @@ def _c3(N=1_000_000, Ns=1_000_000):
     y = (np.exp(-(x * x).sum(axis=1)) + np.cos(3.0 * x[:, 0] * x[:, 1])
          + g.normal(0.0, 0.05, size=N))
     xs = g.uniform(-1.0, 1.0, size=(Ns, 4))
-    return Problem("c3_p4_n8", 4, 8, 0.05, np.ones(4), np.full(4, 1.2), x, y, xs)
+    return Problem("c3_p4_n8", 4, 8, 0.05, np.ones(4), np.full(4, 1.2), x, y, xs,
+                   {"recipe": "x,x*~U[-1,1]^4, y=exp(-|x|^2)+cos(3x1x2)+N(0,0.05^2), eps=1, alpha=1.2"})
 
 
 def _paper_shape(N=10_000, Ns=10_000):
@@ -82,10 +85,25 @@ def _paper_shape(N=10_000, Ns=10_000):
     x = g.uniform(-1.0, 1.0, size=(N, 4))
     y = np.cos(x).sum(axis=1) + g.normal(0.0, 0.1, size=N)
     xs = g.uniform(-1.0, 1.0, size=(Ns, 4))
-    return Problem("paper_p4_n11", 4, 11, 0.1, np.ones(4), np.ones(4), x, y, xs)
+    return Problem("paper_p4_n11", 4, 11, 0.1, np.ones(4), np.ones(4), x, y, xs,
+                   {"recipe": "x,x*~U[-1,1]^4, y=sum_i cos(x_i)+N(0,0.1^2), eps=1, alpha=1"})
 
 
-_CONFIGS = {"c1": _c1, "c2": _c2, "c3": _c3, "paper": _paper_shape}
+def _c5_shape(N=50_000, Ns=2_000, p=5):
+    """One request of the served stream at its largest expansion: p = 5, n = 6
+    (M = 7776), x ~ U[-1,1]^p, y = exp(-|x|^2) + cos(3 x_1 x_2) + N(0, 0.05^2),
+    sigma = 0.05, eps = 1, alpha = 1.2 (the served stream's values), at an N
+    and N_* the oracle finishes in about a minute."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_BASE + 5, p])))
+    x = g.uniform(-1.0, 1.0, size=(N, p))
+    y = (np.exp(-(x * x).sum(axis=1)) + np.cos(3.0 * x[:, 0] * x[:, 1])
+         + g.normal(0.0, 0.05, size=N))
+    xs = g.uniform(-1.0, 1.0, size=(Ns, p))
+    return Problem(f"c5_p{p}_n6", p, 6, 0.05, np.ones(p), np.full(p, 1.2), x, y, xs,
+                   {"recipe": f"x,x*~U[-1,1]^{p}, y=exp(-|x|^2)+cos(3x1x2)+N(0,0.05^2), eps=1, alpha=1.2"})
+
+
+_CONFIGS = {"c1": _c1, "c2": _c2, "c3": _c3, "c5": _c5_shape, "paper": _paper_shape}
 CONFIG_NAMES = tuple(_CONFIGS)
 
 

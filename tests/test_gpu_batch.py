@@ -9,6 +9,7 @@ launch for all mixed problems, captured graph) and the autotuner.
 import numpy as np
 import pytest
 
+from _errs import TOL64, TOL_MEAN_MIXED, TOL_VAR_MIXED, assert_within, errs, fmt
 from oracle import mercer_gp as o
 from paper_2403_12797_amd import binding as B
 from paper_2403_12797_amd import workloads as wl
@@ -76,12 +77,14 @@ def test_batch_equals_single_and_oracle(torch_cuda, prec):
             P = Ps[k]
             f = o.fit(P.x, P.y, P.sigma, P.eps, P.alpha, P.n)
             om, ov = o.predict(f, P.xs)
-            em, ev = rel(means[k].cpu().numpy(), om), rel(vars_[k].cpu().numpy(), ov)
-            print(f"[err] batch {P.name} prec={precs[k]} mean={em:.3e} var={ev:.3e}", flush=True)
+            em, ev = errs(means[k].cpu().numpy(), om), errs(vars_[k].cpu().numpy(), ov)
+            print(f"[err] batch {P.name} prec={precs[k]} mean={fmt(em)} var={fmt(ev)}", flush=True)
             if precs[k] != B.PREC_FP64:
-                assert em <= 1e-5 and ev <= 1e-4
+                assert_within(em, TOL_MEAN_MIXED, "mean")
+                assert_within(ev, TOL_VAR_MIXED, "variance")
             else:
-                assert em <= 1e-10 and ev <= 1e-10
+                assert_within(em, TOL64, "mean")
+                assert_within(ev, TOL64, "variance")
         for m in models:
             m.free()
 
@@ -116,4 +119,5 @@ def test_autotune_then_fit(torch_cuda):
         w, mean, var = single(ctx, torch, P, B.PREC_MIXED_F16)
     f = o.fit(P.x, P.y, P.sigma, P.eps, P.alpha, P.n)
     om, ov = o.predict(f, P.xs)
-    assert rel(mean, om) <= 1e-5 and rel(var, ov) <= 1e-4
+    assert_within(errs(mean, om), TOL_MEAN_MIXED, "mean")
+    assert_within(errs(var, ov), TOL_VAR_MIXED, "variance")

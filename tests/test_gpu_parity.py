@@ -1,26 +1,25 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle
 on the same seeded inputs.
 
-Tolerances (normwise relative, ||got - want||_2 / ||want||_2 per result vector):
+Tolerances, each asserted both normwise (||got - want||_2 / ||want||_2) and
+as max|got - want| / max|want| per result vector (tests/_errs.py):
   FP64 path: 1e-10 on mean, variance and w.
   Mixed paths (Gram as split-BF16 with three terms or as scaled split-FP16
   with two terms; split-BF16 variance; FP64 factorisation, one FP64
   refinement step): 1e-5 on the mean, 1e-4 on the variance.
 """
-import sys
+import os
 
 import numpy as np
 import pytest
 
+from _errs import TOL64, TOL_MEAN_MIXED, TOL_VAR_MIXED, assert_within, errs, fmt
 from oracle import mercer_gp as o
 from paper_2403_12797_amd import binding as B
 from paper_2403_12797_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
-
-TOL64 = 1e-10
-TOL_MEAN_MIXED = 1e-5
-TOL_VAR_MIXED = 1e-4
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def rel(a, b):
@@ -64,17 +63,22 @@ def oracle_fit_predict(P):
     return f, mean, var
 
 
-def check(P, got, want, precision, extra=""):
+def check(P, got, want, precision, extra="", w_ref=None):
+    """Assert the mean and variance (and, FP64, w) within tolerance, both
+    normwise and max-relative; print both (norm/max) on the [err] line."""
     m, gmean, gvar = got
-    f, omean, ovar = want
-    e_mean, e_var = rel(gmean, omean), rel(gvar, ovar)
-    w = m.get(B.MODEL_W)
-    e_w = rel(w, f.w)
-    print(f"[err] {P.name} prec={precision} mean={e_mean:.3e} var={e_var:.3e} w={e_w:.3e} {extra}", flush=True)
+    omean, ovar = want[1], want[2]
+    e_mean, e_var = errs(gmean, omean), errs(gvar, ovar)
+    w = m.weights()
+    e_w = errs(w, want[0].w if w_ref is None else w_ref)
+    print(f"[err] {P.name} prec={precision} mean={fmt(e_mean)} var={fmt(e_var)} w={fmt(e_w)} {extra}", flush=True)
     if precision == B.PREC_FP64:
-        assert e_mean <= TOL64 and e_var <= TOL64 and e_w <= TOL64
+        assert_within(e_mean, TOL64, "mean")
+        assert_within(e_var, TOL64, "variance")
+        assert_within(e_w, TOL64, "w")
     else:
-        assert e_mean <= TOL_MEAN_MIXED and e_var <= TOL_VAR_MIXED
+        assert_within(e_mean, TOL_MEAN_MIXED, "mean")
+        assert_within(e_var, TOL_VAR_MIXED, "variance")
     return e_mean, e_var
 
 
@@ -236,3 +240,30 @@ def test_mixed_gram_range(torch_cuda, ctx, precision, seed, p, n, spread, shift,
     e_A = rel(got[0].get(B.MODEL_A), want[0].A)
     check(P, got, want, precision, extra=f"A={e_A:.3e}")
     assert e_A <= 1e-6
+
+
+@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED, B.PREC_MIXED_F16])
+def test_c5_largest_request_shape(torch_cuda, ctx, precision):
+    """The served stream's largest expansion, p = 5, n = 6 (M = 7776), at
+    N = 50000, N_* = 2000, against the oracle's values in
+    golden/c5_p5_oracle.npz (written by golden/make_shape_goldens.py)."""
+    g = np.load(os.path.join(GOLDEN, "c5_p5_oracle.npz"))
+    P = wl.config("c5")
+    assert int(g["N"]) == P.N and int(g["Ns"]) == P.Ns and int(g["M"]) == P.M
+    got = gpu_fit_predict(torch_cuda, ctx, P, precision)
+    e_b = errs(got[0].get(B.MODEL_B), g["b"])
+    check(P, got, (None, g["mean"], g["var"]), precision, extra=f"b={fmt(e_b)}", w_ref=g["w"])
+    assert_within(e_b, 1e-12, "b")
+
+
+@pytest.mark.parametrize("precision", [B.PREC_FP64, B.PREC_MIXED, B.PREC_MIXED_F16])
+def test_paper_shape(torch_cuda, ctx, precision):
+    """The paper's data-set shape (Sec. 3, the Sec. 4 headline): p = 4, n = 11
+    (M = 14641), N = N_* = 10000, against golden/paper_oracle.npz."""
+    g = np.load(os.path.join(GOLDEN, "paper_oracle.npz"))
+    P = wl.config("paper")
+    assert int(g["N"]) == P.N and int(g["Ns"]) == P.Ns and int(g["M"]) == P.M
+    got = gpu_fit_predict(torch_cuda, ctx, P, precision)
+    e_b = errs(got[0].get(B.MODEL_B), g["b"])
+    check(P, got, (None, g["mean"], g["var"]), precision, extra=f"b={fmt(e_b)}", w_ref=g["w"])
+    assert_within(e_b, 1e-12, "b")

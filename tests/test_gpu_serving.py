@@ -151,3 +151,63 @@ def test_submit_validation(torch_cuda):
             ctx.submit(B.REQ_PREDICT, xs=x)
         with pytest.raises(B.GpError):
             ctx.submit(7, x=x, y=y, params=B.make_params(2, 3, 0.1, 1.0, 1.0))
+
+
+def test_held_models_charged_and_out_of_order_admission(torch_cuda):
+    """A served model the caller holds stays charged to the HBM budget: a
+    large request that fits the budget only without it waits (PENDING)
+    instead of failing, smaller requests submitted after it are admitted
+    ahead of it and complete, and once the held model is freed the large
+    request runs.  Every result equals the synchronous call bitwise."""
+    torch = torch_cuda
+    S = wl.random_problem(201, 2, 12, 5000, 100)      # held model, M = 144
+    G = wl.random_problem(202, 4, 6, 30000, 2000)     # large request, M = 1296
+    smalls = [wl.random_problem(203 + k, 2, 5, 2000, 300) for k in range(3)]
+    prec = B.PREC_MIXED_F16
+    keep = []
+
+    def req(P, kind):
+        x, y, xs = dev(torch, P.x), dev(torch, P.y), dev(torch, P.xs)
+        keep.append((x, y, xs))
+        prm = B.make_params(P.p, P.n, P.sigma, P.eps, P.alpha, prec)
+        keep.append(prm)
+        return dict(x=x, y=y, params=prm, xs=xs if kind != B.REQ_FIT else None)
+
+    with B.Context(0) as c0:
+        ref_G = sync_result(c0, torch, G, prec)
+        ref_s = [sync_result(c0, torch, P, prec) for P in smalls]
+        mS, tS = c0.footprint(B.REQ_FIT, **req(S, B.REQ_FIT))
+        mG, tG = c0.footprint(B.REQ_FIT_PREDICT, **req(G, B.REQ_FIT_PREDICT))
+        ms_, ts_ = c0.footprint(B.REQ_FIT_PREDICT, **req(smalls[0], B.REQ_FIT_PREDICT))
+    budget = mS + mG + tG - 1          # G fits alone, not beside the held model
+    assert mS + tS <= budget and mS + 3 * (ms_ + ts_) <= budget
+    print(f"[case] budget {budget} held {mS} large {mG}+{tG} small {ms_}+{ts_}", flush=True)
+    with B.Context(0, hbm_budget_bytes=budget) as ctx:
+        rid = ctx.submit(B.REQ_FIT, **req(S, B.REQ_FIT))
+        st, held = ctx.poll(rid, wait_us=-1, want_model=True)
+        assert st == B.GP_OK and held is not None
+        assert ctx.memory()[2] == mS
+        with pytest.raises(B.GpError) as ei:          # served models are lean
+            held.get(B.MODEL_A)
+        assert ei.value.status == B.GP_EINVAL
+        assert np.all(np.isfinite(held.weights()))
+        mean_G = torch.full((G.Ns,), float("nan"), dtype=torch.float64, device="cuda")
+        var_G = torch.full_like(mean_G, float("nan"))
+        gid = ctx.submit(B.REQ_FIT_PREDICT, **req(G, B.REQ_FIT_PREDICT), mean=mean_G, var=var_G)
+        outs = []
+        for P in smalls:
+            mean = torch.full((P.Ns,), float("nan"), dtype=torch.float64, device="cuda")
+            var = torch.full_like(mean, float("nan"))
+            outs.append((ctx.submit(B.REQ_FIT_PREDICT, **req(P, B.REQ_FIT_PREDICT), mean=mean, var=var), mean, var))
+        for sid, _, _ in outs:                        # admitted ahead of G
+            st, _ = ctx.poll(sid, wait_us=-1)
+            assert st == B.GP_OK
+        st, _ = ctx.poll(gid, wait_us=200_000)
+        assert st == B.GP_PENDING                     # waits for the held model's memory
+        held.free()
+        st, _ = ctx.poll(gid, wait_us=-1)
+        assert st == B.GP_OK
+        assert ctx.memory()[1:] == (0, 0)
+    assert np.array_equal(mean_G.cpu().numpy(), ref_G[0]) and np.array_equal(var_G.cpu().numpy(), ref_G[1])
+    for (_, mean, var), ref in zip(outs, ref_s):
+        assert np.array_equal(mean.cpu().numpy(), ref[0]) and np.array_equal(var.cpu().numpy(), ref[1])
