@@ -91,13 +91,15 @@ FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chun
   };
   L.lean = lean;
   if (prec_mixed(precision)) {
-    L.g = gram_mixed_plan(N, (int)M, chunk);
+    L.g = gram_mixed_plan(N, p, n, (int)M, precision == GP_PREC_MIXED_F16, chunk);
     if (all_splits) L.g.splits_per_pass = L.g.splits_total, L.g.passes = 1;
     L.gpart = take((size_t)gram_mixed_part_elems(L.g) * 4);
     L.tab32 = take((size_t)gram_mixed_table_elems(N, p, n) * 4);
+    L.hbuf = take((size_t)gram_mixed_hbuf_elems(L.g) * 8);
   } else {
     L.gpart = take((size_t)gram_f64_part_elems(N, (int)M, nullptr) * 8);
     L.tab32 = take(0);
+    L.hbuf = take(0);
   }
   L.vpart = take((size_t)phiT_part_elems(N, (int)M) * 8);
   L.resid = take((size_t)N * 8);
@@ -294,7 +296,7 @@ void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, const
   // a3: A = Phi^T Phi + sigma^2 Lambda^-1
   if (prec_mixed(m->precision)) {
     launch_gram_mixed(x, N, p, n, M, L.g, m->precision == GP_PREC_MIXED_F16, m->tab, m->reg, (float*)(wb + L.gpart),
-                      (float*)(wb + L.tab32), m->A, s, pr);
+                      (float*)(wb + L.tab32), (double*)(wb + L.hbuf), m->A, s, pr);
   } else {
     launch_gram_f64(x, N, p, n, M, m->tab, m->reg, (double*)(wb + L.gpart), m->A, s, pr);
   }

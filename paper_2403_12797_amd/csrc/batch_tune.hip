@@ -86,11 +86,11 @@ gp_status gp_autotune(gp_ctx* ctx, int32_t p, int32_t n, int64_t N, int32_t* chu
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fail(GP_EDEVICE, "stream");
   const int cands[] = {1024, 2048, 4096, 8192, 16384, 32768};
   // workspace for the smallest chunk (most partials) plus x and the tables
-  GramPlan g0 = gram_mixed_plan(N, (int)M, cands[0]);
+  GramPlan g0 = gram_mixed_plan(N, p, n, (int)M, true, cands[0]);
   size_t part_b = (size_t)gram_mixed_part_elems(g0) * 4;
   const size_t tab_b = (size_t)gram_mixed_table_elems(N, p, n) * 4;
   const size_t x_b = (size_t)N * p * 8;
-  const size_t misc = (size_t)(kTabSize + 2 * M + M * M) * 8;
+  const size_t misc = (size_t)(kTabSize + 2 * M + M * M + gram_mixed_hbuf_elems(g0)) * 8;
   char* buf = nullptr;
   if (hipMallocAsync((void**)&buf, part_b + tab_b + x_b + misc + 4096, s) != hipSuccess) {
     hipStreamDestroy(s);
@@ -103,6 +103,7 @@ gp_status gp_autotune(gp_ctx* ctx, int32_t p, int32_t n, int64_t N, int32_t* chu
   double* lam = tab + kTabSize;
   double* reg = lam + M;
   double* A = reg + M;
+  double* hbuf = A + M * M;
   hipLaunchKernelGGL(synth_x_kernel, dim3(1024), dim3(256), 0, s, x, N * p, 12797u);
   EigArgs a;
   memset(&a, 0, sizeof(a));
@@ -119,12 +120,12 @@ gp_status gp_autotune(gp_ctx* ctx, int32_t p, int32_t n, int64_t N, int32_t* chu
   float best_ms = 1e30f;
   for (int c : cands) {
     if (c > 2 * ceil_div(N, 16) * 16 && best) break;
-    GramPlan g = gram_mixed_plan(N, (int)M, c);
+    GramPlan g = gram_mixed_plan(N, p, n, (int)M, true, c);
     if ((size_t)gram_mixed_part_elems(g) * 4 > part_b) continue;
     float tot = 0.0f;
     for (int rep = 0; rep < 3; ++rep) {
       hipEventRecord(e0, s);
-      launch_gram_mixed(x, N, p, n, (int)M, g, true, tab, reg, part, tab32, A, s, nullptr);
+      launch_gram_mixed(x, N, p, n, (int)M, g, true, tab, reg, part, tab32, hbuf, A, s, nullptr);
       hipEventRecord(e1, s);
       hipEventSynchronize(e1);
       float ms = 0.0f;
@@ -181,43 +182,61 @@ gp_status gp_fit_batch(gp_ctx* ctx, int32_t count, const gp_params* params, cons
     off[k] = total;
     total += (Ls[k].total + 255) & ~(size_t)255;
   }
-  // batched Gram work lists of the mixed problems, one per Gram scheme
-  // (FP16 items first, then BF16), each longest first
+  // batched Gram work lists of the mixed problems, one per kernel: Gram
+  // scheme (FP16, BF16) x layout (direct; paired by factor count), each
+  // longest first
   std::vector<GramProb> probs;
   std::vector<GramItem> items;
   std::vector<int> prob_of(count, -1);
-  size_t lds[2] = {0, 0};
-  int nsch[2] = {0, 0};
-  for (int sch = 0; sch < 2; ++sch) {
-    const size_t first = items.size();
-    for (int k = 0; k < count; ++k) {
-      if (params[k].precision != (sch == 0 ? GP_PREC_MIXED_F16 : GP_PREC_MIXED)) continue;
-      const GramPlan& g = Ls[k].g;
-      prob_of[k] = (int)probs.size();
-      GramProb gp{};
-      gp.N = N[k];
-      gp.p = params[k].p;
-      gp.n = params[k].n;
-      gp.M = (int)Ms[k];
-      gp.T = g.T;
-      gp.chunk = g.chunk;
-      probs.push_back(gp);
-      lds[sch] = std::max(lds[sch], gram_mixed_lds_bytes(params[k].p, params[k].n, (int)Ms[k], sch == 0));
-      for (int sp = 0; sp < g.splits_total; ++sp)
-        for (int t = 0; t < g.ntiles; ++t)
-          for (int h = 0; h < 2; ++h) items.push_back(GramItem{prob_of[k], t, h, sp});
-    }
-    // longest first: full chunks before each problem's shorter last chunk
-    std::stable_sort(items.begin() + first, items.end(), [&](const GramItem& a, const GramItem& b) {
-      auto len = [&](const GramItem& i) {
-        const GramProb& q = probs[i.prob];
-        return std::min<int64_t>(q.chunk, q.N - (int64_t)i.split * q.chunk);
-      };
-      return len(a) > len(b);
-    });
-    nsch[sch] = (int)(items.size() - first);
+  struct Group {
+    bool f16, pair;
+    int F;
+    size_t lds;
+    int first, count;
+  };
+  std::vector<Group> groups;
+  for (int k = 0; k < count; ++k) {
+    if (!prec_mixed(params[k].precision)) continue;
+    const GramPlan& g = Ls[k].g;
+    prob_of[k] = (int)probs.size();
+    GramProb gp{};
+    gp.N = N[k];
+    gp.p = params[k].p;
+    gp.n = params[k].n;
+    gp.M = (int)Ms[k];
+    gp.T = g.T;
+    gp.chunk = g.chunk;
+    gp.ntiles = g.ntiles;
+    gp.p1 = g.p1;
+    gp.S1 = g.S1;
+    gp.S2 = g.S2;
+    gp.T2 = g.T2;
+    probs.push_back(gp);
   }
-  const size_t meta = probs.size() * sizeof(GramProb) + items.size() * sizeof(GramItem) + 256;
+  for (int sch = 0; sch < 2; ++sch)
+    for (int F : {0, 2, 4, 6}) {   // F = 0: direct layout
+      Group gr{sch == 0, F != 0, F, 0, (int)items.size(), 0};
+      for (int k = 0; k < count; ++k) {
+        if (prob_of[k] < 0 || (params[k].precision == GP_PREC_MIXED_F16) != gr.f16) continue;
+        const GramPlan& g = Ls[k].g;
+        if ((g.pair != 0) != gr.pair || (g.pair && pair_factors(params[k].p, g) != F)) continue;
+        gr.lds = std::max(gr.lds, gram_mixed_lds_bytes(params[k].p, params[k].n, (int)Ms[k], g, gr.f16));
+        for (int sp = 0; sp < g.splits_total; ++sp)
+          for (int t = 0; t < g.ntiles; ++t)
+            for (int h = 0; h < (g.pair ? 1 : 2); ++h) items.push_back(GramItem{prob_of[k], t, h, sp});
+      }
+      // longest first: full chunks before each problem's shorter last chunk
+      std::stable_sort(items.begin() + gr.first, items.end(), [&](const GramItem& a, const GramItem& b) {
+        auto len = [&](const GramItem& i) {
+          const GramProb& q = probs[i.prob];
+          return std::min<int64_t>(q.chunk, q.N - (int64_t)i.split * q.chunk);
+        };
+        return len(a) > len(b);
+      });
+      gr.count = (int)items.size() - gr.first;
+      if (gr.count) groups.push_back(gr);
+    }
+  const size_t meta = probs.size() * sizeof(GramProb) + items.size() * sizeof(GramItem) + 256 + 16 * sizeof(int);
   char* ws = nullptr;
   hipError_t e = hipMallocAsync((void**)&ws, total + meta + 512, s);
   if (e != hipSuccess) {
@@ -231,7 +250,7 @@ gp_status gp_fit_batch(gp_ctx* ctx, int32_t count, const gp_params* params, cons
     }
   GramProb* probs_dev = (GramProb*)(ws + total);
   GramItem* items_dev = (GramItem*)((char*)probs_dev + ((probs.size() * sizeof(GramProb) + 255) & ~(size_t)255));
-  int* counter = (int*)((char*)items_dev + ((items.size() * sizeof(GramItem) + 255) & ~(size_t)255));
+  int* counter = (int*)((char*)items_dev + ((items.size() * sizeof(GramItem) + 255) & ~(size_t)255));   // one per group
   if (!probs.empty()) {
     hipMemcpyAsync(probs_dev, probs.data(), probs.size() * sizeof(GramProb), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(items_dev, items.data(), items.size() * sizeof(GramItem), hipMemcpyHostToDevice, s);
@@ -264,10 +283,15 @@ gp_status gp_fit_batch(gp_ctx* ctx, int32_t count, const gp_params* params, cons
       hipEventRecord(ev_heads[f], fs[f]);
       hipStreamWaitEvent(cs, ev_heads[f], 0);
     }
-    // one persistent Gram launch per scheme for all mixed problems
-    if (nsch[0]) launch_gram_mixed_batch(probs_dev, items_dev, nsch[0], true, counter, lds[0], cs, nullptr);
-    if (nsch[1])
-      launch_gram_mixed_batch(probs_dev, items_dev + nsch[0], nsch[1], false, counter + 1, lds[1], cs, nullptr);
+    // one persistent Gram launch per group of mixed problems
+    for (size_t q = 0; q < groups.size(); ++q) {
+      const Group& gr = groups[q];
+      if (gr.pair)
+        launch_gram_pair_batch(probs_dev, items_dev + gr.first, gr.count, gr.f16, gr.F, counter + q, gr.lds, cs,
+                               nullptr);
+      else
+        launch_gram_mixed_batch(probs_dev, items_dev + gr.first, gr.count, gr.f16, counter + q, gr.lds, cs, nullptr);
+    }
     hipEventRecord(ev_fork, cs);
     for (int f = 0; f < kForks; ++f) hipStreamWaitEvent(fs[f], ev_fork, 0);
     for (int k = 0; k < count; ++k) {
@@ -275,8 +299,9 @@ gp_status gp_fit_batch(gp_ctx* ctx, int32_t count, const gp_params* params, cons
       hipStream_t fk = fs[k % kForks];
       const int M = (int)Ms[k];
       if (prec_mixed(params[k].precision)) {
-        launch_gram_mixed_reduce((const float*)(ws + off[k] + Ls[k].gpart), Ls[k].g.splits_total, Ls[k].g.T, M,
-                                 m->reg, true, m->A, fk);
+        launch_gram_mixed_reduce((const float*)(ws + off[k] + Ls[k].gpart), Ls[k].g.splits_total, params[k].p,
+                                 params[k].n, M, Ls[k].g, m->reg, true, true, (double*)(ws + off[k] + Ls[k].hbuf),
+                                 m->A, fk);
       } else {
         launch_gram_f64(x[k], N[k], params[k].p, params[k].n, M, m->tab, m->reg, (double*)(ws + off[k] + Ls[k].gpart),
                         m->A, fk, nullptr);

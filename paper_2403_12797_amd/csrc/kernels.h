@@ -40,33 +40,56 @@ void launch_gram_f64(const double* x, int64_t N, int p, int n, int M, const doub
 // partials per pass.  tab32 holds gram_mixed_table_elems() floats: the 1-D
 // tables and their per-row maxima, written by launch_gram_mixed_table(),
 // which must run before launch_gram_mixed() on the same stream.
+// Two layouts of the work:
+//  * direct: upper 256 x 256 tiles of Phi^T Phi, each in two 128-column halves;
+//  * paired (pair = 1, pair_gram.hip): H = Psi1^T Psi2 over the pair tuples of
+//    two groups of dimensions (s = n(n+1)/2 pairs per dimension, p1 = p / 2
+//    leading dimensions, S1 = s^p1, S2 = s^(p - p1)), in T1 x T2 items of
+//    256 x 128; A is gathered from H (hbuf, S1 x S2 FP64).
 struct GramPlan {
   int T, ntiles, chunk, splits_total, splits_per_pass, passes;
+  int pair, p1, s, S1, S2, T1, T2;
 };
-GramPlan gram_mixed_plan(int64_t N, int M, int chunk /* <= 0: default */);
+GramPlan gram_mixed_plan(int64_t N, int p, int n, int M, bool f16, int chunk /* <= 0: default */);
 int64_t gram_mixed_part_elems(const GramPlan& g);
+int64_t gram_mixed_hbuf_elems(const GramPlan& g);
 int64_t gram_mixed_table_elems(int64_t N, int p, int n);
-size_t gram_mixed_lds_bytes(int p, int n, int M, bool f16);
+size_t gram_mixed_lds_bytes(int p, int n, int M, const GramPlan& g, bool f16);
 void launch_gram_mixed_table(const double* x, int64_t N, int p, int n, const double* tab, float* tab32,
                              hipStream_t s);
 void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const GramPlan& g, bool f16,
-                       const double* tab, const double* reg, float* part, float* tab32, double* A,
+                       const double* tab, const double* reg, float* part, float* tab32, double* hbuf, double* A,
                        hipStream_t s, Prof* prof = nullptr);
-void launch_gram_mixed_reduce(const float* part, int splits, int T, int M, const double* reg,
-                              bool first, double* A, hipStream_t s);
+// Sum `splits` partials into A (first: A = reg on the diagonal + sum; else
+// A += sum); paired plans sum into hbuf and gather A on the last pass.
+void launch_gram_mixed_reduce(const float* part, int splits, int p, int n, int M, const GramPlan& g,
+                              const double* reg, bool first, bool last, double* hbuf, double* A, hipStream_t s);
 // Batched: one persistent launch over the work items of many problems that
-// share a Gram scheme.
+// share a Gram scheme and layout.
 struct GramProb {
   const float* tab32;
   float* part;
   int64_t N;
-  int p, n, M, T, chunk, pad;
+  int p, n, M, T, chunk, ntiles;
+  int p1, S1, S2, T2;   // paired layout
 };
 struct GramItem {
   int prob, tile, h, split;
 };
 void launch_gram_mixed_batch(const GramProb* probs_dev, const GramItem* items_dev, int nitems, bool f16,
                              int* counter, size_t lds, hipStream_t s, Prof* prof = nullptr);
+// paired layout (pair_gram.hip): plan, kernels and reduction
+bool pair_plan(int p, int n, int M, bool f16, GramPlan& g);
+void pair_plan_splits(int64_t N, GramPlan& g, int chunk);
+size_t pair_gram_lds_bytes(int p, int n, const GramPlan& g, bool f16);
+int pair_factors(int p, const GramPlan& g);
+void launch_gram_pair(int64_t N, int p, int n, int M, const GramPlan& g, bool f16, const double* reg, float* part,
+                      const float* tab32, double* H, double* A, hipStream_t s, Prof* prof);
+void launch_pair_reduce(const float* part, int splits, int p, int n, int M, const GramPlan& g, const double* reg,
+                        bool first, bool last, double* H, double* A, hipStream_t s);
+void launch_gram_pair_batch(const GramProb* probs_dev, const GramItem* items_dev, int nitems, bool f16, int F,
+                            int* counter, size_t lds, hipStream_t s, Prof* prof);
+hipError_t configure_pair_kernels();
 
 // a4: blocked Cholesky in place (lower), block inverses Dinv[M/64][64*64],
 // info (device int, 0 = ok, else failing column + 1).

@@ -22,70 +22,17 @@
 //   B (16 x 32): lane l holds B[8*(l/32) .. +7][l % 32]
 //   D (32 x 32): element r of the lane's float16 is
 //                D[8*(r/4) + 4*(l/32) + (r%4)][l % 32]
-#include "kernels.h"
+#include <stdlib.h>
+#include <string.h>
+
+#include "mixed_common.h"
 
 namespace mgp {
 
-__device__ __forceinline__ f32x16 mfma_bf16(const bf16x8& a, const bf16x8& b, const f32x16& c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-}
-
-// Round-to-nearest-even FP32 -> BF16 of two values, packed (lo half = a).
-__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-  bf16x2_t v = {(__bf16)a, (__bf16)b};
-  return __builtin_bit_cast(uint32_t, v);
-}
-// The same with the packed word kept opaque to the compiler (an empty asm):
-// otherwise it re-derives each unpacked half with a second conversion of
-// one value, which costs a VALU instruction per half.
-__device__ __forceinline__ uint32_t pack_bf16x2_opaque(float a, float b) {
-  uint32_t w = pack_bf16x2(a, b);
-  asm volatile("" : "+v"(w));
-  return w;
-}
-__device__ __forceinline__ float bf16lo_f(uint32_t w) { return __uint_as_float(w << 16); }
-__device__ __forceinline__ float bf16hi_f(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
-
-// Three-term BF16 split of a pair of FP32 values; returns packed (hi, mid, lo).
-__device__ __forceinline__ void split3(float a, float b, uint32_t& h, uint32_t& m, uint32_t& l) {
-  h = pack_bf16x2_opaque(a, b);
-  const float ra = a - bf16lo_f(h), rb = b - bf16hi_f(h);
-  m = pack_bf16x2_opaque(ra, rb);
-  const float sa = ra - bf16lo_f(m), sb = rb - bf16hi_f(m);
-  l = pack_bf16x2(sa, sb);
-}
-__device__ __forceinline__ void split2(float a, float b, uint32_t& h, uint32_t& l) {
-  h = pack_bf16x2(a, b);
-  l = pack_bf16x2(a - bf16lo_f(h), b - bf16hi_f(h));
-}
-
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ f32x16 mfma_f16(const f16x8& a, const f16x8& b, const f32x16& c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
-}
-// Round-to-nearest-even FP32 -> FP16 of two values, packed (lo half = a).
-__device__ __forceinline__ uint32_t pack_f16x2(float a, float b) {
-  f16x2 v = {(_Float16)a, (_Float16)b};
-  return __builtin_bit_cast(uint32_t, v);
-}
-// Two-term FP16 split of a pair of FP32 values; returns packed (hi, lo).
-__device__ __forceinline__ void split2h(float a, float b, uint32_t& h, uint32_t& l) {
-  h = pack_f16x2(a, b);
-  asm volatile("" : "+v"(h));
-  const f16x2 hv = __builtin_bit_cast(f16x2, h);
-  l = pack_f16x2(a - (float)hv[0], b - (float)hv[1]);
-}
-
 // ================================================================ a3 mixed Gram
 // Pre-pass: the 1-D eigenfunctions of every sample, computed in FP64 and
-// stored as FP32 in stage-contiguous blocks of 16 samples:
-//   tab32[s][j*n + k][16]  (s = sample / 16), zero for samples >= N,
-// followed by kGmMaxWords words: the largest |value| of each row j*n + k
-// over all samples (FP32 bits, which order like the magnitudes).
-constexpr int kGmKC = 16;
-constexpr int kGmMaxWords = GP_MAX_P * GP_MAX_N;
+// stored as FP32 in stage-contiguous blocks of 16 samples, with the row
+// maxima (layout in mixed_common.h).
 constexpr int kGmTableBlocks = 1024;
 
 // Grid-stride over (stage, dimension, sample-in-stage); the 16 lanes of one
@@ -139,20 +86,8 @@ __global__ void __launch_bounds__(256) phi1d_table_kernel(const double* __restri
     if (smax[r]) atomicMax(&tmax[r], smax[r]);
 }
 
-// Exponent e(j,k) of a row's scale from its largest magnitude (zero rows:
-// 0), the last dimension's rows raised by 15; bounded so that 2^e stays a
-// normal FP32 number.
+// Last dimension's rows are raised by a further 2^15 (see the scaling note).
 constexpr int kGmF16Top = 15;
-__device__ __forceinline__ int gm_row_exp(unsigned maxbits, bool last) {
-  int e = 0;
-  if (maxbits) {
-    int E;
-    frexpf(__uint_as_float(maxbits), &E);
-    e = -E;
-  }
-  e += last ? kGmF16Top : 0;
-  return min(max(e, -120), 100);
-}
 
 // Gram work-group: rows I*256..+256 and columns J*256 + h*128..+128 (half h
 // of the J-block) of Phi^T Phi, I <= J, over one chunk of samples.  512
@@ -185,9 +120,19 @@ constexpr int64_t kGmPartCap = 8ll << 30;                   // bytes of partials
 // 16-bit elements per stage buffer: [term][slot][sample]
 __host__ __device__ constexpr int gm_stage_elems(bool f16) { return (f16 ? 2 : 3) * kG2Slots * kG2SlotPitch; }
 
-GramPlan gram_mixed_plan(int64_t N, int M, int chunk) {
-  GramPlan g;
+// Paired layout where pair_plan accepts it, unless MGP_GRAM_LAYOUT=direct.
+static bool pair_allowed() {
+  const char* v = getenv("MGP_GRAM_LAYOUT");
+  return !(v && strcmp(v, "direct") == 0);
+}
+
+GramPlan gram_mixed_plan(int64_t N, int p, int n, int M, bool f16, int chunk) {
+  GramPlan g{};
   g.T = (int)ceil_div(M, kGmT);
+  if (pair_allowed() && pair_plan(p, n, M, f16, g)) {
+    pair_plan_splits(N, g, chunk);
+    return g;
+  }
   g.ntiles = g.T * (g.T + 1) / 2;
   if (chunk <= 0) {
     // enough work items to fill the GPU several times over: chunks of 1024..32768 samples
@@ -205,14 +150,11 @@ GramPlan gram_mixed_plan(int64_t N, int M, int chunk) {
   return g;
 }
 
-int64_t gram_mixed_part_elems(const GramPlan& g) { return (int64_t)g.splits_per_pass * g.ntiles * kGmT * kGmT; }
-
-// Zero stages past the end let the kernel prefetch without bounds tests: a
-// work-group reads at most four stages past its last one.
-constexpr int kGmTabPad = 4;
-__host__ __device__ inline int64_t gm_max_offset(int64_t N, int p, int n) {
-  return (ceil_div(N, kGmKC) + kGmTabPad) * p * n * kGmKC;
+int64_t gram_mixed_part_elems(const GramPlan& g) {
+  return (int64_t)g.splits_per_pass * g.ntiles * (g.pair ? kGmT * kG2H : kGmT * kGmT);
 }
+int64_t gram_mixed_hbuf_elems(const GramPlan& g) { return g.pair ? (int64_t)g.S1 * g.S2 : 0; }
+
 int64_t gram_mixed_table_elems(int64_t N, int p, int n) { return gm_max_offset(N, p, n) + kGmMaxWords; }
 
 // Prefix rows per stage: I-block prefixes then J-half prefixes (L consecutive
@@ -332,7 +274,7 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
   // (each thread stores one table row's 4 samples, scaled by the row's 2^e)
   float4 treg0, treg1;
   const int trow = tid / (kGmKC / 4);
-  const float tsc = tid < tchunks ? ldexpf(1.0f, gm_row_exp(tmax[trow], trow >= (P - 1) * n)) : 0.0f;
+  const float tsc = tid < tchunks ? ldexpf(1.0f, gm_row_exp(tmax[trow], trow >= (P - 1) * n ? kGmF16Top : 0)) : 0.0f;
   auto load_tab = [&](int64_t gst, float4& r) {
     if (tid < tchunks) r = reinterpret_cast<const float4*>(tab32 + gst * rows * kGmKC)[tid];
   };
@@ -478,7 +420,7 @@ __device__ __forceinline__ void gram_item(unsigned char* smraw, const float* __r
     if (c < M && (sl < kGmT || genJ)) {
       int rem = c;
       for (int j = P - 1; j >= 0; --j) {
-        e += gm_row_exp(tmax[j * n + rem % n], j == P - 1);
+        e += gm_row_exp(tmax[j * n + rem % n], j == P - 1 ? kGmF16Top : 0);
         rem /= n;
       }
     }
@@ -669,7 +611,9 @@ __global__ void __launch_bounds__(256) gram_mixed_reduce_kernel(const float* __r
   }
 }
 
-size_t gram_mixed_lds_bytes(int p, int n, int M, bool f16) { return gram_lds_bytes(p, n, M, f16); }
+size_t gram_mixed_lds_bytes(int p, int n, int M, const GramPlan& g, bool f16) {
+  return g.pair ? pair_gram_lds_bytes(p, n, g, f16) : gram_lds_bytes(p, n, M, f16);
+}
 
 void launch_gram_mixed_table(const double* x, int64_t N, int p, int n, const double* tab, float* tab32,
                              hipStream_t s) {
@@ -681,8 +625,12 @@ void launch_gram_mixed_table(const double* x, int64_t N, int p, int n, const dou
 }
 
 void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const GramPlan& g, bool f16,
-                       const double* tab, const double* reg, float* part, float* tab32, double* A, hipStream_t s,
-                       Prof* prof) {
+                       const double* tab, const double* reg, float* part, float* tab32, double* hbuf, double* A,
+                       hipStream_t s, Prof* prof) {
+  if (g.pair) {
+    launch_gram_pair(N, p, n, M, g, f16, reg, part, tab32, hbuf, A, s, prof);
+    return;
+  }
   for (int ps = 0; ps < g.passes; ++ps) {
     const int split0 = ps * g.splits_per_pass;
     const int cnt = std::min(g.splits_per_pass, g.splits_total - split0);
@@ -692,13 +640,18 @@ void launch_gram_mixed(const double* x, int64_t N, int p, int n, int M, const Gr
                        part);
     prof_mark(prof, GP_PH_GRAM, false, s);
     prof_mark(prof, GP_PH_GRAM_REDUCE, true, s);
-    launch_gram_mixed_reduce(part, cnt, g.T, M, reg, ps == 0, A, s);
+    launch_gram_mixed_reduce(part, cnt, p, n, M, g, reg, ps == 0, ps == g.passes - 1, hbuf, A, s);
     prof_mark(prof, GP_PH_GRAM_REDUCE, false, s);
   }
 }
 
-void launch_gram_mixed_reduce(const float* part, int splits, int T, int M, const double* reg, bool first, double* A,
-                              hipStream_t s) {
+void launch_gram_mixed_reduce(const float* part, int splits, int p, int n, int M, const GramPlan& g,
+                              const double* reg, bool first, bool last, double* hbuf, double* A, hipStream_t s) {
+  if (g.pair) {
+    launch_pair_reduce(part, splits, p, n, M, g, reg, first, last, hbuf, A, s);
+    return;
+  }
+  const int T = g.T;
   const int T64 = (int)ceil_div(M, 64);
   hipLaunchKernelGGL(gram_mixed_reduce_kernel, dim3(T64 * (T64 + 1) / 2), dim3(256), 0, s, part, splits, T, M, reg,
                      first ? 1 : 0, A);
@@ -843,7 +796,37 @@ __host__ __device__ inline int pm_pdig_entries(int p, int n, int M) {
   return e <= kPdigMax ? e : 0;
 }
 
-template <int TN, int P, bool G>
+// Instruction-scheduling pattern of a stage (SCH): 0 leaves it to the
+// compiler; 1..3 interleave the MFMAs with the stage's LDS reads and vector
+// work through scheduling-group barriers.
+template <int SCH>
+__device__ __forceinline__ void pm_sched() {
+  if constexpr (SCH == 1) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 12, 0);   // operand reads
+#pragma unroll
+    for (int i = 0; i < 24; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two vector instructions
+    }
+  } else if constexpr (SCH == 2) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);    // operands of the first product
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);  // the remaining reads
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS stores among them
+    }
+  } else if constexpr (SCH == 3) {
+    __builtin_amdgcn_iglp_opt(0);
+  }
+}
+
+template <int TN, int P, bool G, int SCH = 0>
 __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     const double* __restrict__ xs, int64_t Ns, int n, int M, const double* __restrict__ tab,
     const uint16_t* __restrict__ midx, const uint32_t* __restrict__ pdesc_words, const __bf16* __restrict__ lpieces,
@@ -1134,6 +1117,7 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
         lin_store(nb + C::PHI, R0, R1);
         lin_load(s3.rb, s3.k, R0, R1);
       }
+      pm_sched<SCH>();
       if (pre_next) make_pre(s2.k, pdst);
       if (s0.k == s0.ns - 1) {
         // squares of this column block, summed over the lane's column
@@ -1226,7 +1210,21 @@ static PredictKernel predict_kernel_p(int p) {
   }
 }
 // G: the thread's column group (CPT = 16 TN / 512 columns) divides n
+// (MGP_VAR_SCHED = 1..3 selects a scheduling pattern for TN = 256, p = 4
+// with grouped descriptors; a tuning knob, default 0)
+static int var_sched() {
+  const char* v = getenv("MGP_VAR_SCHED");
+  return v ? atoi(v) : 0;
+}
 static PredictKernel predict_kernel_for(int TN, int p, bool G) {
+  if (TN == 256 && p == 4 && G) {
+    switch (var_sched()) {
+      case 1: return predict_var_mixed_kernel<256, 4, true, 1>;
+      case 2: return predict_var_mixed_kernel<256, 4, true, 2>;
+      case 3: return predict_var_mixed_kernel<256, 4, true, 3>;
+      default: break;
+    }
+  }
   if (TN == 256) return G ? predict_kernel_p<256, true>(p) : predict_kernel_p<256, false>(p);
   return G ? predict_kernel_p<128, true>(p) : predict_kernel_p<128, false>(p);
 }
@@ -1273,6 +1271,14 @@ hipError_t configure_kernels() {
   hipError_t e = hipSuccess;
   for (const void* k : {(const void*)gram_mixed_kernel<true>, (const void*)gram_mixed_kernel<false>,
                         (const void*)gram_mixed_batch_kernel<true>, (const void*)gram_mixed_batch_kernel<false>}) {
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+  }
+  e = configure_pair_kernels();
+  if (e != hipSuccess) return e;
+  for (const void* k : {(const void*)predict_var_mixed_kernel<256, 4, true, 1>,
+                        (const void*)predict_var_mixed_kernel<256, 4, true, 2>,
+                        (const void*)predict_var_mixed_kernel<256, 4, true, 3>}) {
     e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
   }
