@@ -6,6 +6,9 @@
 //   A (16 x 4):  A[l % 16][l / 16]
 //   B (4 x 16):  B[l / 16][l % 16]
 //   D (16 x 16): element q of the lane's double4 is D[4*q + l/16][l % 16]
+#include <stdlib.h>
+#include <string.h>
+
 #include "kernels.h"
 
 namespace mgp {
@@ -269,6 +272,114 @@ __global__ void __launch_bounds__(kPfThreads) potrf_diag_kernel(double* __restri
   }
 }
 
+// The same factor and inverse with two waves.  Lane i of wave H holds
+// row i of the block, columns 32H .. 32H+31, in registers.  Step k: the
+// wave that owns column k takes the pivot sqrt(B[k][k]) from lane k,
+// scales its entry of column k and publishes the column in LDS (two
+// alternating buffers, one barrier per step); both waves then subtract
+// l_i l_j from their entries j > k, l_j read back as a broadcast.  Entries
+// above the diagonal collect values that are never used; a failing pivot is
+// recorded and replaced by 1 so the unrolled steps run to the end.  Then
+// X = L^-1 with L in LDS (transposed, so a column is a contiguous row):
+// lane c of wave H forms rows 32H .. 32H+31 of column c by forward
+// substitution, wave 1 after subtracting the contributions of rows 0..31,
+// which wave 0 leaves in LDS.  Rows and columns past the matrix are the
+// identity.
+constexpr int kPdNone = kNb + 1;
+template <int H>
+__device__ __forceinline__ void potrf_diag2_body(double* __restrict__ A, int M, int k0, int nb,
+                                                 double* __restrict__ Dinv, double (*colv)[kNb], double* Lt,
+                                                 double* Xs, int* sbad) {
+  const int i = threadIdx.x & 63;
+  double a[32];
+  // row j of the (symmetric) block, read coalesced: lane i takes B[j][i] = B[i][j]
+#pragma unroll
+  for (int jl = 0; jl < 32; ++jl) {
+    const int j = 32 * H + jl;
+    a[jl] = (i < nb && j < nb) ? A[(int64_t)(k0 + j) * M + k0 + i] : (i == j ? 1.0 : 0.0);
+  }
+  int bad = 0;
+#pragma unroll
+  for (int k = 0; k < kNb; ++k) {
+    if ((k >> 5) == H) {
+      double d = __shfl(a[k - 32 * H], k);
+      if (!(d > 0.0) || !isfinite(d)) {   // same value in every lane
+        if (!bad) bad = k + 1;
+        d = 1.0;
+      }
+      const double piv = sqrt(d);
+      const double l = i > k ? a[k - 32 * H] / piv : (i == k ? piv : 0.0);
+      a[k - 32 * H] = l;
+      colv[k & 1][i] = l;
+    }
+    __syncthreads();
+    if (k < 32 * H + 31) {
+      const double li = colv[k & 1][i];
+#pragma unroll
+      for (int jl = 0; jl < 32; ++jl)
+        if (32 * H + jl > k) a[jl] = fma(-li, colv[k & 1][32 * H + jl], a[jl]);
+    }
+  }
+  if (bad && i == 0) atomicMin(sbad, bad);
+#pragma unroll
+  for (int jl = 0; jl < 32; ++jl) {
+    const int j = 32 * H + jl;
+    Lt[j * kNbLd + i] = j <= i ? a[jl] : 0.0;
+  }
+  __syncthreads();
+  if (*sbad != kPdNone) return;
+  // L into rows 32H .. 32H+31 of the block (lane i = column; zeros above)
+  for (int r = 32 * H; r < 32 * H + 32 && r < nb; ++r)
+    if (i < nb) A[(int64_t)(k0 + r) * M + k0 + i] = Lt[i * kNbLd + r];
+  double x[32];
+  if (H == 1) __syncthreads();   // rows 0..31 of X are in Xs
+#pragma unroll
+  for (int rl = 0; rl < 32; ++rl) {
+    const int r = 32 * H + rl;
+    double v = r == i ? 1.0 : 0.0;
+    if (H == 1) {
+#pragma unroll
+      for (int j = 0; j < 32; ++j) v = fma(-Lt[j * kNbLd + r], Xs[j * kNbLd + i], v);
+    }
+    x[rl] = v;
+  }
+#pragma unroll
+  for (int rl = 0; rl < 32; ++rl) {
+    const int r = 32 * H + rl;
+    x[rl] = x[rl] / Lt[r * kNbLd + r];
+#pragma unroll
+    for (int ql = rl + 1; ql < 32; ++ql) x[ql] = fma(-Lt[r * kNbLd + 32 * H + ql], x[rl], x[ql]);
+  }
+  if (H == 0) {
+#pragma unroll
+    for (int rl = 0; rl < 32; ++rl) Xs[rl * kNbLd + i] = x[rl];
+    __syncthreads();
+  }
+  double* D = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
+#pragma unroll
+  for (int rl = 0; rl < 32; ++rl) {
+    const int r = 32 * H + rl;
+    D[r * kNb + i] = (r < nb && i < nb && i <= r) ? x[rl] : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A, int M, int k0,
+                                                          double* __restrict__ Dinv, int* __restrict__ info) {
+  __shared__ double colv[2][kNb];
+  __shared__ double Lt[kNb * kNbLd];   // Lt[j][i] = L[i][j]
+  __shared__ double Xs[32 * kNbLd];    // rows 0..31 of X
+  __shared__ int sbad;
+  if (*info) return;
+  if (threadIdx.x == 0) sbad = kPdNone;
+  const int nb = min(kNb, M - k0);
+  if ((threadIdx.x >> 6) == 0)
+    potrf_diag2_body<0>(A, M, k0, nb, Dinv, colv, Lt, Xs, &sbad);
+  else
+    potrf_diag2_body<1>(A, M, k0, nb, Dinv, colv, Lt, Xs, &sbad);
+  __syncthreads();
+  if (threadIdx.x == 0 && sbad != kPdNone) *info = k0 + sbad;
+}
+
 // One 64x64 output tile of C = sum_k A[m][k] B[k][n] with A, B row-major in
 // global memory (lda, ldb), k in [kb, ke), rows m >= mv / columns n >= nv and
 // k >= kv read as zero.  4 waves, each a 32x32 quarter (2x2 MFMA blocks).
@@ -395,9 +506,20 @@ __global__ void __launch_bounds__(256) syrk_trailing_kernel(double* __restrict__
       }
 }
 
+// (MGP_CHOL_DIAG=block selects the 512-thread diagonal factor; a tuning
+// knob, the two-wave factor is the default)
+static bool chol_diag_block() {
+  const char* v = getenv("MGP_CHOL_DIAG");
+  return v && strcmp(v, "block") == 0;
+}
+
 void launch_cholesky(double* A, int M, double* Dinv, int* info, hipStream_t s) {
+  const bool blk = chol_diag_block();
   for (int k0 = 0; k0 < M; k0 += kNb) {
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(kPfThreads), 0, s, A, M, k0, Dinv, info);
+    if (blk)
+      hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(kPfThreads), 0, s, A, M, k0, Dinv, info);
+    else
+      hipLaunchKernelGGL(potrf_diag2_kernel, dim3(1), dim3(128), 0, s, A, M, k0, Dinv, info);
     const int rest = M - k0 - kNb;
     if (rest <= 0) break;
     const int tb = (int)ceil_div(rest, kNb);
