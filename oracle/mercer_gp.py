@@ -56,7 +56,8 @@ import scipy.linalg as sla
 __all__ = [
     "se_scalars", "gamma_coeffs", "eigenvalues_1d", "hermite_physicists",
     "eigenfunctions_1d", "multi_indices", "eigenvalues_nd", "eigenfunctions_nd",
-    "se_ard_kernel", "truncated_kernel", "Fit", "fit", "predict",
+    "se_ard_kernel", "truncated_kernel", "Fit", "fit", "predict", "predict_cov",
+    "log_marginal_likelihood", "log_marginal_likelihood_nxn",
     "posterior_woodbury_W", "posterior_truncated_nxn", "posterior_exact_se",
 ]
 
@@ -242,9 +243,47 @@ def predict(f: Fit, Xs, chunk: int = 4096):
     return mean, var
 
 
+def predict_cov(f: Fit, Xs, chunk: int = 4096):
+    """Full predictive covariance of the latent f_* (eq. (12) in weight-space
+    form): Sigma_* = sigma^2 Phi_* A^-1 Phi_*^T, N_* x N_*.  Its diagonal is
+    predict()'s variance."""
+    Xs = np.atleast_2d(np.asarray(Xs, dtype=np.float64))
+    Ps = eigenfunctions_nd(Xs, f.eps, f.alpha, f.n, f.order)
+    Z = sla.lu_solve(f.lu, Ps.T)                        # A^-1 Phi_*^T
+    return f.sigma ** 2 * (Ps @ Z)
+
+
+def log_marginal_likelihood(f: Fit, y):
+    """log p(y) under the truncated-kernel GP prior of (7)-(8):
+    y ~ N(0, S), S = Phi Lambda Phi^T + sigma^2 I (zero prior mean), written
+    with the M x M system of the weight-space form instead of S itself:
+      y^T S^-1 y = (y^T y - b^T w) / sigma^2            (Woodbury, as (10))
+      log det S  = (N - M) log sigma^2 + sum_m log Lambda_m + log det A
+    (the matrix determinant lemma with A = Phi^T Phi + sigma^2 Lambda^-1), so
+      log p(y) = -(y^T y - b^T w) / (2 sigma^2) - log det S / 2 - N log(2 pi) / 2.
+    log det A is the sum of log |u_ii| over the LU factor of A (A is SPD)."""
+    y = np.asarray(y, dtype=np.float64).reshape(-1)
+    N, M = y.shape[0], f.lam.shape[0]
+    s2 = f.sigma * f.sigma
+    logdet_A = float(np.sum(np.log(np.abs(np.diag(f.lu[0])))))
+    logdet_S = (N - M) * math.log(s2) + float(np.sum(np.log(f.lam))) + logdet_A
+    quad = (float(y @ y) - float(f.b @ f.w)) / s2
+    return -0.5 * quad - 0.5 * logdet_S - 0.5 * N * math.log(2.0 * math.pi)
+
+
 # --------------------------------------------------------------------------
 # Alternative formulations (small N only), used to pin F1
 # --------------------------------------------------------------------------
+def log_marginal_likelihood_nxn(X, y, sigma, eps, alpha, n):
+    """log N(y; 0, K~ + sigma^2 I) with the N x N truncated kernel (7),
+    evaluated by its definition (Cholesky of the N x N covariance)."""
+    y = np.asarray(y, dtype=np.float64).reshape(-1)
+    S = truncated_kernel(X, X, eps, alpha, n) + sigma * sigma * np.eye(y.shape[0])
+    L = np.linalg.cholesky(S)
+    a = sla.solve_triangular(L, y, lower=True)
+    return -0.5 * float(a @ a) - float(np.sum(np.log(np.diag(L)))) - 0.5 * y.shape[0] * math.log(2.0 * math.pi)
+
+
 def posterior_woodbury_W(X, y, Xs, sigma, eps, alpha, n):
     """F2: the paper's literal FAGP form (11)-(12) with
     Lambda_bar = Lambda^-1 + Phi^T Sigma^-1 Phi and

@@ -302,3 +302,66 @@ def test_pin_catches_wrong_multi_index_order(monkeypatch):
     _with(monkeypatch, "eigenfunctions_nd", swapped)
     with pytest.raises(AssertionError):
         test_tensor_factorisation()
+
+
+# ---------------------------------------------------------------- full covariance and log marginal likelihood
+@pytest.mark.parametrize("p,n,eps,alpha", [(1, 10, 1.0, 1.0), (2, 5, [1.0, 1.3], [1.2, 0.9]), (3, 3, 0.8, 1.0)])
+def test_full_covariance_equals_nxn_truncated_posterior(p, n, eps, alpha):
+    """predict_cov (weight space, eq. (12)) vs the N x N form (eq. (9)) on the
+    whole N* x N* matrix, and its diagonal is predict()'s variance."""
+    X, y, Xs = _small(30 + p, p)
+    f = o.fit(X, y, 0.1, eps, alpha, n)
+    C1 = o.predict_cov(f, Xs)
+    _, C3 = o.posterior_truncated_nxn(X, y, Xs, 0.1, eps, alpha, n)
+    assert rel(C1, C3) <= 1e-10
+    assert np.allclose(C1, C1.T, rtol=0, atol=1e-15 * np.abs(C1).max())
+    _, v1 = o.predict(f, Xs)
+    assert rel(np.diag(C1), v1) <= 1e-13
+    # positive semi-definite up to rounding
+    assert np.linalg.eigvalsh(0.5 * (C1 + C1.T)).min() >= -1e-12 * np.abs(C1).max()
+
+
+@pytest.mark.parametrize("p,n,sigma,eps,alpha", [(1, 10, 0.1, 1.0, 1.0), (2, 5, 0.05, [1.0, 1.3], [1.2, 0.9]),
+                                                 (3, 3, 0.2, 0.8, 1.0), (2, 6, 0.1, 1.0, 1.2)])
+def test_log_marginal_likelihood_equals_gaussian_density(p, n, sigma, eps, alpha):
+    """The weight-space log marginal likelihood (Woodbury + determinant lemma)
+    against log N(y; 0, K~ + sigma^2 I) evaluated two ways on the N x N
+    covariance: by its Cholesky, and by scipy's multivariate normal."""
+    from scipy.stats import multivariate_normal
+    X, y, _ = _small(40 + p, p)
+    f = o.fit(X, y, sigma, eps, alpha, n)
+    lml = o.log_marginal_likelihood(f, y)
+    ref = o.log_marginal_likelihood_nxn(X, y, sigma, eps, alpha, n)
+    S = o.truncated_kernel(X, X, eps, alpha, n) + sigma * sigma * np.eye(len(y))
+    lib = multivariate_normal(mean=np.zeros(len(y)), cov=S).logpdf(y)
+    assert abs(lml - ref) <= 1e-10 * abs(ref)
+    assert abs(ref - lib) <= 1e-10 * abs(lib)
+
+
+def test_log_marginal_likelihood_single_term_closed_form():
+    """p = 1, n = 1: S = lambda_1 phi phi^T + sigma^2 I, so by the determinant
+    lemma log det S = N log sigma^2 + log(1 + lambda_1 |phi|^2 / sigma^2) and
+    y^T S^-1 y = (|y|^2 - (phi.y)^2 lambda_1 / (sigma^2 + lambda_1 |phi|^2)) / sigma^2."""
+    X, y, _ = _small(50, 1)
+    sigma = 0.3
+    f = o.fit(X, y, sigma, 1.0, 1.0, 1)
+    phi = o.eigenfunctions_1d(X[:, 0], 1.0, 1.0, 1)[:, 0]
+    lam = o.eigenvalues_1d(1.0, 1.0, 1)[0]
+    s2, N = sigma * sigma, len(y)
+    pp, py = float(phi @ phi), float(phi @ y)
+    logdet = N * np.log(s2) + np.log1p(lam * pp / s2)
+    quad = (float(y @ y) - py * py * lam / (s2 + lam * pp)) / s2
+    want = -0.5 * quad - 0.5 * logdet - 0.5 * N * np.log(2 * np.pi)
+    assert abs(o.log_marginal_likelihood(f, y) - want) <= 1e-12 * abs(want)
+
+
+def test_pin_catches_dropped_eigenvalue_logdet(monkeypatch):
+    """A log marginal likelihood that forgets the sum of log Lambda in
+    log det S must fail the Gaussian-density pin."""
+    real = o.log_marginal_likelihood
+
+    def broken(f, y):
+        return real(f, y) + 0.5 * float(np.sum(np.log(f.lam)))
+    monkeypatch.setattr(o, "log_marginal_likelihood", broken)
+    with pytest.raises(AssertionError):
+        test_log_marginal_likelihood_equals_gaussian_density(2, 5, 0.05, [1.0, 1.3], [1.2, 0.9])
