@@ -122,6 +122,24 @@ gp_status gp_fit(gp_ctx *ctx, const gp_params *params, const double *x, const do
 gp_status gp_predict(gp_ctx *ctx, const gp_model *model, const double *xs, int64_t Ns,
                      double *mean, double *var, void *stream);
 
+/* Predict without allocating, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): as gp_predict, same kernels and results, but the
+ * prediction's workspace (the variance partial sums) is a fixed device array
+ * of GP_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; no hipMalloc / hipFree or other allocating call is
+ * made.  The array is shared by every call on a GPU and keeps the last
+ * call's contents (nothing in it needs to start at zero): calls that overlap
+ * on one GPU, from any thread or stream, race and must be serialised by the
+ * caller.  Profiling events are not recorded.  Errors: as gp_predict, and
+ * GP_EINVAL when Ns is too large for the array (a mixed model needs
+ * 8 * Ns * g + 256 bytes, g <= ceil(M / 256) partial-sum groups, g = 1 once
+ * Ns >= 128 * 1024; the FP64 path g <= ceil(M / 64), g = 1 once Ns >=
+ * 64 * 2048).                                                                */
+#define GP_NOALLOC_SCRATCH_BYTES (32u << 20)
+gp_status gp_predict_noalloc(gp_ctx *ctx, const gp_model *model, const double *xs, int64_t Ns,
+                             double *mean, double *var, void *stream);
+
 /* Free a model (waits for the device work that uses it).  NULL accepted.
  * A served model's bytes leave the context's admission budget here.        */
 gp_status gp_model_free(gp_model *model);

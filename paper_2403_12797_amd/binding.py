@@ -25,7 +25,7 @@ MAX_P, MAX_N, MAX_M = 8, 64, 16384
 EXPORTED = ["gp_ctx_create", "gp_ctx_destroy", "gp_fit", "gp_predict", "gp_model_free", "gp_model_info",
             "gp_model_get", "gp_submit", "gp_poll", "gp_last_error", "gp_profile_enable", "gp_profile_read",
             "gp_fit_batch", "gp_predict_batch", "gp_autotune", "gp_model_weights", "gp_request_footprint",
-            "gp_ctx_memory"]
+            "gp_ctx_memory", "gp_predict_noalloc"]
 PHASES = ["gram", "gram_reduce", "phiT", "chol", "trtri", "solve", "split", "predict", "predict_mean",
           "predict_reduce"]
 
@@ -65,6 +65,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "gp_ctx_destroy": (i32, [vp]),
         "gp_fit": (i32, [vp, C.POINTER(GpParams), vp, vp, i64, vp, C.POINTER(vp)]),
         "gp_predict": (i32, [vp, vp, vp, i64, vp, vp, vp]),
+        "gp_predict_noalloc": (i32, [vp, vp, vp, i64, vp, vp, vp]),
         "gp_model_free": (i32, [vp]),
         "gp_model_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), C.POINTER(i32), dp]),
         "gp_model_get": (i32, [vp, i32, dp, i64]),
@@ -218,6 +219,14 @@ class Context:
         Ns = xs.shape[0] if xs is not None else 0
         _check(load().gp_predict(self.handle, model.handle, _ptr(xs), Ns, _ptr(mean), _ptr(var),
                                  _stream(stream)))
+        return mean, var
+
+    def predict_noalloc(self, model: Model, xs, mean=None, var=None, stream=None):
+        """gp_predict_noalloc: as predict, workspace from the library's fixed
+        device array (no allocation; overlapping calls on one GPU race)."""
+        Ns = xs.shape[0] if xs is not None else 0
+        _check(load().gp_predict_noalloc(self.handle, model.handle, _ptr(xs), Ns, _ptr(mean), _ptr(var),
+                                         _stream(stream)))
         return mean, var
 
     def autotune(self, p: int, n: int, N: int) -> int:

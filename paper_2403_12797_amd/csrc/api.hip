@@ -308,11 +308,11 @@ void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, const
 }
 
 void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* mean, double* var, void* ws,
-                     hipStream_t s) {
+                     hipStream_t s, bool profile) {
   if (Ns <= 0) return;
   const int p = m->p, n = m->n, M = (int)m->M;
   const double s2 = m->sigma * m->sigma;
-  Prof* pr = &m->ctx->prof;
+  Prof* pr = profile ? &m->ctx->prof : nullptr;
   if (prec_mixed(m->precision)) {
     launch_predict_mixed(xs, Ns, p, n, M, m->tab, m->midx, m->pdesc, m->linv_pieces, m->w, s2, (double*)ws, mean,
                          var, s, pr);
@@ -324,6 +324,30 @@ void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* me
     }
     if (var) launch_predict_var_f64(xs, Ns, p, n, M, m->tab, m->Linv, s2, (double*)ws, var, s, pr);
   }
+}
+
+// ---------------------------------------------------------------- scratch
+// Device memory of gp_predict_noalloc: the variance partial sums (the only
+// workspace a prediction uses) live in this file-scope array, which every
+// GPU the library runs on holds until the process ends.  In host code the
+// name `scratch` is a host-side stand-in, not a device address: the device
+// address is looked up once per device (scratch_init, from gp_ctx_create with
+// that device current) and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[GP_NOALLOC_SCRATCH_BYTES];
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchDevices] = {};
+
+static gp_status scratch_init(int device) {
+  if (device < 0 || device >= kScratchDevices) return fail(GP_EDEVICE, "device %d has no scratch slot", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return GP_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(GP_EDEVICE, "device address of the scratch array: %s", hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  return GP_OK;
 }
 
 }  // namespace mgp
@@ -346,6 +370,10 @@ gp_status gp_ctx_create(int device, size_t hbm_budget_bytes, gp_ctx** out) {
   if (device < 0 || device >= count) return fail(GP_EINVAL, "device %d not in 0..%d", device, count - 1);
   HIP_TRY(hipSetDevice(device));
   HIP_TRY(configure_kernels());
+  {
+    const gp_status sst = scratch_init(device);
+    if (sst != GP_OK) return sst;
+  }
   size_t freeb = 0, totalb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totalb));
   gp_ctx* c = new gp_ctx();
@@ -435,6 +463,24 @@ gp_status gp_predict(gp_ctx* ctx, const gp_model* model, const double* xs, int64
   HIP_TRY(hipMallocAsync(&ws, wsb, s));
   enqueue_predict(model, xs, Ns, mean, var, ws, s);
   HIP_TRY(hipFreeAsync(ws, s));
+  HIP_TRY(hipGetLastError());
+  return GP_OK;
+}
+
+gp_status gp_predict_noalloc(gp_ctx* ctx, const gp_model* model, const double* xs, int64_t Ns, double* mean,
+                             double* var, void* stream) {
+  if (!ctx || !model) return fail(GP_EINVAL, "ctx/model is NULL");
+  if (Ns < 0) return fail(GP_EINVAL, "Ns=%lld must be >= 0", (long long)Ns);
+  if (Ns == 0 || (!mean && !var)) return GP_OK;
+  if (!xs) return fail(GP_EINVAL, "xs is NULL");
+  const size_t wsb = predict_workspace_bytes(Ns, model->M, model->precision);
+  if (wsb > (size_t)GP_NOALLOC_SCRATCH_BYTES)
+    return fail(GP_EINVAL, "Ns=%lld at M=%lld needs %zu bytes of scratch; gp_predict_noalloc holds %zu",
+                (long long)Ns, (long long)model->M, wsb, (size_t)GP_NOALLOC_SCRATCH_BYTES);
+  void* ws = (ctx->device >= 0 && ctx->device < kScratchDevices) ? g_scratch_ptr[ctx->device] : nullptr;
+  if (!ws) return fail(GP_EDEVICE, "no scratch address for device %d", ctx->device);
+  HIP_TRY(hipSetDevice(ctx->device));
+  enqueue_predict(model, xs, Ns, mean, var, ws, (hipStream_t)stream, false);
   HIP_TRY(hipGetLastError());
   return GP_OK;
 }

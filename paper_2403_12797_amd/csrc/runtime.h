@@ -135,8 +135,9 @@ gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, bool lean, h
 void model_release(gp_model* m, hipStream_t s, bool sync_device);
 void enqueue_fit(gp_model* m, const double* x, const double* y, int64_t N, const FitLayout& L, void* ws,
                  hipStream_t s);
+// (profile = false: no phase events, as for the no-allocation entry point)
 void enqueue_predict(const gp_model* m, const double* xs, int64_t Ns, double* mean, double* var, void* ws,
-                     hipStream_t s);
+                     hipStream_t s, bool profile = true);
 gp_status scheduler_start(gp_ctx* ctx);
 void scheduler_stop(gp_ctx* ctx);
 // Consume one pending injected fault of this name (from MGP_FAULT or
