@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the served Poisson stream (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--batched", type=int, default=256,
+                    help="problems of the batched leg (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -178,6 +180,49 @@ def served_stream(torch, rate, seconds, warm=2.0):
                         "N* log-U[1e2,1e5], mixed precision (FP16 Gram), 4 stream slots"}
 
 
+def batched_leg(torch, count, steps=2):
+    """The batched workload: `count` independent problems with p ~ U{1,2,3},
+    one n ~ U{4..12} per problem, N log-uniform in [1e3, 2e5], N* = N,
+    x ~ N(0, I_p), y = sum_d sin(k_d x_d) + N(0, 0.1^2), eps ~ U[0.5, 2],
+    alpha = 1, sigma = 0.1; mixed precision (FP16 Gram).  A step is one
+    gp_fit_batch (one persistent Gram launch per kernel group, the rest in a
+    captured graph) and one gp_predict_batch over all problems, inputs
+    resident in HBM; value = sum(N + N*) / seconds per step."""
+    from paper_2403_12797_amd import binding as B
+    from paper_2403_12797_amd import workloads as wl
+    Ps = wl.batched_problems(count)
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    dx = [(d(P.x), d(P.y), P.p, P.n, P.sigma, P.eps, P.alpha) for P in Ps]
+    xs = [d(P.xs) for P in Ps]
+    means = [torch.empty(P.Ns, dtype=torch.float64, device="cuda") for P in Ps]
+    vars_ = [torch.empty(P.Ns, dtype=torch.float64, device="cuda") for P in Ps]
+    torch.cuda.synchronize()
+    ctx = B.Context(0)
+
+    def step():
+        models = ctx.fit_batch(dx, precision=B.PREC_MIXED_F16)
+        ctx.predict_batch(models, xs, means, vars_)
+        torch.cuda.synchronize()
+        for m in models:
+            m.free()
+
+    step()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    dt = (time.perf_counter() - t0) / steps
+    ctx.close()
+    pts = sum(P.N + P.Ns for P in Ps)
+    Ms = sorted(P.M for P in Ps)
+    return {"problems": count, "points": pts, "value": pts / dt, "unit": "points/s", "ms_per_step": dt * 1e3,
+            "steps": steps, "M_median": Ms[len(Ms) // 2], "M_max": Ms[-1],
+            "workload": "256 independent problems, p~U{1,2,3}, n~U{4..12}, N log-U[1e3,2e5], N*=N, x~N(0,I_p), "
+                        "mixed precision (FP16 Gram); gp_fit_batch + gp_predict_batch"}
+
+
 def cpu_baseline(P_full, target_s):
     """The FP64 oracle (as it is) on bounded samples of the same workload.
 
@@ -234,36 +279,78 @@ def cpu_baseline(P_full, target_s):
                       f"full workload from t = F + c (N + N*) fitted to the two samples"}
 
 
-def gram_source_fingerprint():
-    """sha256 of the code of the Gram kernel section of mixed_path.hip
-    (constants, table kernel, plan, work item and kernels; not the launchers),
-    with comment lines, trailing comments and blank lines dropped."""
-    src = open(os.path.join(ROOT, "paper_2403_12797_amd", "csrc", "mixed_path.hip")).read()
-    a = src.index("// ================================================================ a3 mixed Gram")
-    b = src.index("__global__ void reset_counter_kernel")
+# Source sections whose code a counter record is tied to: (file, first
+# banner, end marker); the fingerprint is the sha256 of the code between
+# them with comment lines, trailing comments and blank lines dropped.
+SECTIONS = {
+    "variance": ("mixed_path.hip", "// ================================================================ a5 mixed predict",
+                 "__global__ void predict_mixed_reduce_kernel"),
+    "gram_pair": ("pair_gram.hip", "constexpr int kPgT", "// Single problem: grid"),
+}
+
+
+def source_fingerprint(section):
+    fname, start, end = SECTIONS[section]
+    src = open(os.path.join(ROOT, "paper_2403_12797_amd", "csrc", fname)).read()
     code = []
-    for line in src[a:b].splitlines():
+    for line in src[src.index(start):src.index(end)].splitlines():
         line = line.split("//", 1)[0].rstrip()
         if line:
             code.append(line)
     return hashlib.sha256("\n".join(code).encode()).hexdigest()
 
 
-def gram_traffic(P, scheme):
-    """HBM bytes per Gram launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE record, scaled by the copy-kernel calibration; None when the
-    record is for another workload or the kernel source has changed since."""
-    path = os.path.join(ROOT, "profiles", "gram_mixed_kernel_c3_hbm.json")
+def kernel_traffic(P, section, record):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record (profiles/<record>), scaled by the copy-kernel
+    calibration; None when the record is for another workload or the
+    kernel's code has changed since."""
+    path = os.path.join(ROOT, "profiles", record)
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None, "no counter record"
-    if rec.get("N") != P.N or rec.get("M") != P.M or rec.get("workload") != P.name or rec.get("gram") != scheme:
-        return None, "counter record is for another workload or Gram scheme"
-    if rec.get("source_fingerprint") != gram_source_fingerprint():
+    if rec.get("N") != P.N or rec.get("Ns") != P.Ns or rec.get("M") != P.M or rec.get("workload") != P.name:
+        return None, "counter record is for another workload"
+    if rec.get("source_fingerprint") != source_fingerprint(section):
         return None, "kernel changed since the counters were taken"
     kib = sum(rec["fetch_kib_per_launch"]) * rec["fetch_factor"] + sum(rec["write_kib_per_launch"]) * rec["write_factor"]
     return kib * 1024.0 / len(rec["fetch_kib_per_launch"]), "bytes per launch, " + os.path.basename(path)
+
+
+def gram_layout(P, f16):
+    """The Gram layout the library picks for this shape (mirrors pair_plan in
+    pair_gram.hip): paired when p >= 2, the tabulated digit counts and the
+    LDS fit, and it has fewer 256 x 128 work items per chunk than the direct
+    upper triangle; MGP_GRAM_LAYOUT=direct forces the direct layout."""
+    if os.environ.get("MGP_GRAM_LAYOUT") == "direct" or P.p < 2:
+        return None
+    n, p = P.n, P.p
+    s, p1 = n * (n + 1) // 2, p // 2
+    S1, S2 = s ** p1, s ** (p - p1)
+    if n ** p1 > 1024 or n ** (p - p1) > 1024:
+        return None
+    npre1 = min(S1, 256) // s + 2 if p1 > 1 else 0
+    npre2 = min(S2, 128) // s + 2 if p - p1 > 1 else 0
+    ndi = 2 * s + npre1 + npre2
+    lds = 2 * (2 if f16 else 3) * 384 * 16 * 2 + 3 * (p * n + 1) * 20 * 4 + 2 * (ndi + 2) * 20 * 4 + 384 * 4 + ndi * 12 + 16
+    T = -(-P.M // 256)
+    T1, T2 = -(-S1 // 256), -(-S2 // 128)
+    if lds > 159 * 1024 or T1 * T2 >= T * (T + 1):
+        return None
+    F = 2 * max(1, p - p1 - 1)
+    return {"s": s, "p1": p1, "S1": S1, "S2": S2, "T1": T1, "T2": T2, "F": F}
+
+
+def variance_issued_flops(P):
+    """MFMA flops the variance kernel issues: three products per pair over
+    256-point tiles x 256-wide L^-1 row blocks x the 16-column stages each
+    row block reaches (columns c <= its last row)."""
+    Mc = -(-P.M // 16)
+    RB = -(-P.M // 256)
+    stages = sum(min((rb + 1) * 16, Mc) for rb in range(RB))
+    pts = -(-P.Ns // 256) * 256
+    return 3 * 2 * pts * 256 * 16 * stages
 
 
 def main():
@@ -316,15 +403,29 @@ def main():
     ctx.close()
 
     steps = a.steps
+    # dominant kernel: the variance contraction (a5); the Gram (a3) beside it
+    pv_ms, pv_cnt = prof_mx["predict"]
+    var_launch_ms = pv_ms / pv_cnt
+    var_flops = P.Ns * P.M * (P.M + 1)        # per launch: per test point M(M+1) (triangular L^-1 phi, squares)
+    var_achieved = var_flops / (var_launch_ms * 1e-3)
+    var_traffic, var_traffic_note = kernel_traffic(P, "variance", f"predict_var_mixed_kernel_{P.name}_hbm.json")
+    tn = 256 if (P.p * P.n + 1 + 2 * (15 // P.n + 2)) * 256 * 4 + 2 * 2 * 16 * 512 * 2 + 2 * 256 * 8 + 8192 <= 159 * 1024 \
+        else 128
+    var_kernel = f"predict_var_mixed_kernel<{tn}, {P.p}, {'true' if P.n % (16 * tn // 512) == 0 else 'false'}>"
     g_ms, g_cnt = prof_mx["gram"]
-    launches_per_step = g_cnt / steps
-    avg_launch_ms = g_ms / g_cnt
-    flops_per_step = P.N * P.M * (P.M + 1)            # useful Gram flops (upper triangle, mul+add)
-    achieved = flops_per_step / (g_ms / steps * 1e-3)
-    issued = (3.0 if f16 else 6.0) * achieved * (2.0 * 65536 * (((P.M + 255) // 256) * ((P.M + 255) // 256 + 1) // 2)) / \
-        (P.M * (P.M + 1))
-    pv_ms = prof_mx["predict"][0] / steps
-    traffic, traffic_note = gram_traffic(P, a.gram)
+    gram_launch_ms = g_ms / g_cnt
+    lay = gram_layout(P, f16)
+    nt = 3 if f16 else 6
+    if lay:
+        gram_flops = 2 * P.N * lay["s"] ** P.p            # H = Psi1^T Psi2: N s^p multiply-adds
+        ceil32 = lambda v: -(-v // 32) * 32
+        gram_issued = nt * 2 * P.N * ceil32(lay["S1"]) * ceil32(lay["S2"])
+        gram_kernel = f"gram_pair_kernel<{'true' if f16 else 'false'}, {lay['F']}, 0>"
+    else:
+        gram_flops = P.N * P.M * (P.M + 1)
+        T = -(-P.M // 256)
+        gram_issued = nt * 2 * P.N * 65536 * T * (T + 1) // 2
+        gram_kernel = f"gram_mixed_kernel<{'true' if f16 else 'false'}>"
     out = {
         "metric": METRIC, "value": (P.N + P.Ns) / dt_mx, "unit": "points/s", "n_gpus": 1, "steps": steps,
         "warmup": a.warmup, "ms_per_step": dt_mx * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -333,22 +434,33 @@ def main():
         "config": {"workload": f"{P.name}: p={P.p}, n={P.n}, M={P.M}, N={P.N}, N*={P.Ns}, "
                                f"{P.meta.get('recipe', '')}; "
                                f"fit + predict(mean, var); Gram "
-                               + ("split-FP16 MFMA on power-of-two-scaled Phi (2 terms, 3 products)" if f16 else
+                               + ("paired (pair tuples of two dimension groups) " if lay else "direct ")
+                               + ("split-FP16 MFMA on power-of-two-scaled operands (2 terms, 3 products)" if f16 else
                                   "split-BF16 MFMA (3 terms, 6 products)")
                                + "; variance split-BF16 MFMA (2 terms, 3 products); FP64 Cholesky + 1 refinement",
                    "precision": "mixed_f16" if f16 else "mixed"},
-        "roofline": {"kernel": f"gram_mixed_kernel<{'true' if f16 else 'false'}>", "bound": "mfma", "achieved": achieved / 1e12,
-                     "peak": PEAK_16 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_16,
-                     "traffic": traffic, "traffic_note": traffic_note, "launches_per_step": launches_per_step,
-                     "avg_launch_ms": avg_launch_ms, "algorithmic_flops_per_step": flops_per_step,
-                     "mfma_issue_frac": issued / PEAK_16,
-                     "predict_kernel_frac": (P.Ns * P.M * (P.M + 1)) / (pv_ms * 1e-3) / PEAK_16},
+        "roofline": {"kernel": var_kernel, "bound": "mfma", "achieved": var_achieved / 1e12,
+                     "peak": PEAK_16 / 1e12, "unit": "TFLOP/s", "frac": var_achieved / PEAK_16,
+                     "traffic": var_traffic, "traffic_note": var_traffic_note, "launches_per_step": pv_cnt / steps,
+                     "avg_launch_ms": var_launch_ms, "algorithmic_flops_per_launch": var_flops,
+                     "mfma_issue_frac": variance_issued_flops(P) / (var_launch_ms * 1e-3) / PEAK_16},
+        "gram": {"kernel": gram_kernel, "layout": "paired" if lay else "direct", "bound": "mfma",
+                 "avg_launch_ms": gram_launch_ms, "launches_per_step": g_cnt / steps,
+                 "algorithmic_flops_per_launch": gram_flops,
+                 "achieved": gram_flops / (gram_launch_ms * 1e-3) / 1e12, "unit": "TFLOP/s",
+                 "frac": gram_flops / (gram_launch_ms * 1e-3) / PEAK_16,
+                 "mfma_issue_frac": gram_issued / (gram_launch_ms * 1e-3) / PEAK_16,
+                 "direct_gram_equivalent_frac": P.N * P.M * (P.M + 1) / (gram_launch_ms * 1e-3) / PEAK_16},
         "phases_ms": {k: round(v[0] / steps, 3) for k, v in prof_mx.items() if v[1]},
         "other_gram_scheme": alt,
         "fp64_path": fp64,
         "served": None,
+        "batched": None,
         "cpu_baseline": None if a.no_cpu else cpu_baseline(P, a.cpu_target_s),
     }
+    if a.batched > 0:
+        print(f"[bench] batched leg: {a.batched} problems", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg(torch, a.batched)
     if a.serve_seconds > 0:
         print(f"[bench] served stream {a.serve_seconds:.0f} s at {a.serve_rate:.0f} req/s", file=sys.stderr,
               flush=True)

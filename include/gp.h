@@ -170,6 +170,57 @@ enum { GP_MODEL_W = 0, GP_MODEL_LAMBDA = 1, GP_MODEL_A = 2, GP_MODEL_B = 3, GP_M
        GP_MODEL_LINV = 5 };
 gp_status gp_model_get(const gp_model *model, int32_t what, double *host_out, int64_t count);
 
+/* Log marginal likelihood of the data a model was fitted to, log p(y) for
+ * y ~ N(0, Phi Lambda Phi^T + sigma^2 I) (the truncated-kernel GP of eqs.
+ * 7-8 with zero prior mean), formed at fit time from the M x M system:
+ *   log p(y) = -(y^T y - b^T w) / (2 sigma^2)
+ *              - ((N - M) log sigma^2 + sum_m log Lambda_m + log det A) / 2
+ *              - N log(2 pi) / 2,
+ * A = L L^T = Phi^T Phi + sigma^2 Lambda^-1, b = Phi^T y, w = A^-1 b (Woodbury
+ * and the matrix determinant lemma).  Mixed-precision models use their
+ * mixed A.  Synchronous.  Errors: GP_EINVAL, GP_EDEVICE.                    */
+gp_status gp_model_lml(const gp_model *model, double *lml);
+
+/* Full predictive covariance of the latent f_* at a block of Ns test points
+ * (eq. 12): Sigma_* = sigma^2 Phi_* A^-1 Phi_*^T = sigma^2 Z Z^T with
+ * Z = Phi_* L^-T, in FP64 on FP64 MFMA (Phi_* of the block is materialised,
+ * Ns x M, in a workspace of 16 Ns M bytes).  xs: device [Ns*p]; cov: device,
+ * row-major with row pitch ld >= Ns, both triangles written; its diagonal
+ * equals gp_predict's variance up to rounding (the FP64 path bit for bit in
+ * exact arithmetic).  Needs the model's FP64 L^-1: models from gp_fit and
+ * gp_fit_batch (all precisions), not the lean served models.  Enqueued on
+ * `stream`; returns without waiting.  Ns <= 2^20.
+ * Errors: GP_EINVAL, GP_ENOMEM, GP_EDEVICE.                                 */
+gp_status gp_predict_cov(gp_ctx *ctx, const gp_model *model, const double *xs, int64_t Ns,
+                         double *cov, int64_t ld, void *stream);
+
+/* Hyperparameter learning (the paper's Sec. 5 outlook): maximise the log
+ * marginal likelihood (gp_model_lml) over log eps, optionally log alpha and
+ * log sigma, by Nelder-Mead from `start` (initial simplex steps of 0.3 in
+ * each log-parameter).  Every evaluation is a full gp_fit on the device at
+ * start's precision, p and n; a fit that fails as not SPD counts as -inf.
+ *  max_evals    fits at most (<= 0: 150)
+ *  per_dim      0: one eps (and alpha) shared by all dimensions, starting
+ *               from start->eps[0] (alpha[0]); 1: one per dimension (ARD)
+ *  learn_alpha  nonzero: alpha is learnt, else kept at start's
+ *  learn_sigma  nonzero: sigma is learnt, else kept at start's
+ *  tol          stop once the simplex's log likelihoods span <= tol
+ *               (<= 0: 1e-6)
+ * Outputs (each may be NULL): eps_out[p], alpha_out[p], *sigma_out of the
+ * best point, *lml_out its log likelihood, *evals_out the fits made.  x, y as
+ * in gp_fit.  Synchronous.  Errors: GP_EINVAL, GP_ENOMEM, GP_EDEVICE,
+ * GP_ENOTSPD (no evaluated point was SPD).                                  */
+typedef struct {
+  int32_t max_evals;
+  int32_t per_dim;
+  int32_t learn_alpha;
+  int32_t learn_sigma;
+  double tol;
+} gp_learn_opts;
+gp_status gp_learn(gp_ctx *ctx, const gp_params *start, const double *x, const double *y, int64_t N,
+                   const gp_learn_opts *opts, void *stream, double *eps_out, double *alpha_out,
+                   double *sigma_out, double *lml_out, int32_t *evals_out);
+
 /* Batched fit of `count` independent problems (uneven N, p, n allowed):
  * params/x/y/N/out_models are arrays of length count (x[k], y[k] device
  * arrays as in gp_fit).  The mixed-precision problems of each Gram scheme

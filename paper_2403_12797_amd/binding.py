@@ -25,7 +25,7 @@ MAX_P, MAX_N, MAX_M = 8, 64, 16384
 EXPORTED = ["gp_ctx_create", "gp_ctx_destroy", "gp_fit", "gp_predict", "gp_model_free", "gp_model_info",
             "gp_model_get", "gp_submit", "gp_poll", "gp_last_error", "gp_profile_enable", "gp_profile_read",
             "gp_fit_batch", "gp_predict_batch", "gp_autotune", "gp_model_weights", "gp_request_footprint",
-            "gp_ctx_memory", "gp_predict_noalloc"]
+            "gp_ctx_memory", "gp_predict_noalloc", "gp_model_lml", "gp_predict_cov", "gp_learn"]
 PHASES = ["gram", "gram_reduce", "phiT", "chol", "trtri", "solve", "split", "predict", "predict_mean",
           "predict_reduce"]
 
@@ -40,6 +40,11 @@ class GpRequest(C.Structure):
     _fields_ = [("kind", C.c_int32), ("params", GpParams), ("x", C.c_void_p), ("y", C.c_void_p),
                 ("N", C.c_int64), ("model", C.c_void_p), ("xs", C.c_void_p), ("Ns", C.c_int64),
                 ("mean", C.c_void_p), ("var", C.c_void_p)]
+
+
+class GpLearnOpts(C.Structure):
+    _fields_ = [("max_evals", C.c_int32), ("per_dim", C.c_int32), ("learn_alpha", C.c_int32),
+                ("learn_sigma", C.c_int32), ("tol", C.c_double)]
 
 
 class GpError(RuntimeError):
@@ -66,6 +71,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "gp_fit": (i32, [vp, C.POINTER(GpParams), vp, vp, i64, vp, C.POINTER(vp)]),
         "gp_predict": (i32, [vp, vp, vp, i64, vp, vp, vp]),
         "gp_predict_noalloc": (i32, [vp, vp, vp, i64, vp, vp, vp]),
+        "gp_model_lml": (i32, [vp, dp]),
+        "gp_predict_cov": (i32, [vp, vp, vp, i64, vp, i64, vp]),
+        "gp_learn": (i32, [vp, C.POINTER(GpParams), vp, vp, i64, C.POINTER(GpLearnOpts), vp, dp, dp, dp, dp,
+                           C.POINTER(i32)]),
         "gp_model_free": (i32, [vp]),
         "gp_model_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), C.POINTER(i32), dp]),
         "gp_model_get": (i32, [vp, i32, dp, i64]),
@@ -161,6 +170,12 @@ class Model:
         _check(load().gp_model_get(self.handle, what, out.ctypes.data_as(C.POINTER(C.c_double)), size))
         return out.reshape(M, M) if size == M * M else out
 
+    def lml(self) -> float:
+        """gp_model_lml: log marginal likelihood of the data the model was fitted to."""
+        v = C.c_double()
+        _check(load().gp_model_lml(self.handle, C.byref(v)))
+        return v.value
+
     def weights(self):
         """w on the host (C-order multi-index)."""
         import numpy as np
@@ -228,6 +243,29 @@ class Context:
         _check(load().gp_predict_noalloc(self.handle, model.handle, _ptr(xs), Ns, _ptr(mean), _ptr(var),
                                          _stream(stream)))
         return mean, var
+
+    def predict_cov(self, model: Model, xs, cov, stream=None):
+        """gp_predict_cov: full predictive covariance of a block into cov
+        (Ns x Ns float64 CUDA tensor, row pitch = cov.shape[1])."""
+        Ns = xs.shape[0]
+        _check(load().gp_predict_cov(self.handle, model.handle, _ptr(xs), Ns, _ptr(cov), cov.shape[1],
+                                     _stream(stream)))
+        return cov
+
+    def learn(self, x, y, *, p, n, sigma, eps, alpha, precision=PREC_FP64, max_evals=150, per_dim=False,
+              learn_alpha=True, learn_sigma=True, tol=1e-6, stream=None):
+        """gp_learn: returns (eps[p], alpha[p], sigma, lml, evals) of the best point."""
+        import numpy as np
+        prm = make_params(p, n, sigma, eps, alpha, precision)
+        opts = GpLearnOpts(max_evals, int(per_dim), int(learn_alpha), int(learn_sigma), tol)
+        e_out = np.zeros(p)
+        a_out = np.zeros(p)
+        s_out, lml, ev = C.c_double(), C.c_double(), C.c_int32()
+        N = y.shape[0]
+        _check(load().gp_learn(self.handle, C.byref(prm), _ptr(x), _ptr(y), N, C.byref(opts), _stream(stream),
+                               e_out.ctypes.data_as(C.POINTER(C.c_double)), a_out.ctypes.data_as(C.POINTER(C.c_double)),
+                               C.byref(s_out), C.byref(lml), C.byref(ev)))
+        return e_out, a_out, s_out.value, lml.value, ev.value
 
     def autotune(self, p: int, n: int, N: int) -> int:
         c = C.c_int32()

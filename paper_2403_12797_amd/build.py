@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmercergp.so")
-SOURCES = ["tables_vec.hip", "fp64_path.hip", "mixed_path.hip", "pair_gram.hip", "api.hip", "scheduler.hip", "batch_tune.hip"]
+SOURCES = ["tables_vec.hip", "fp64_path.hip", "mixed_path.hip", "pair_gram.hip", "posterior.hip", "learn.hip", "api.hip", "scheduler.hip", "batch_tune.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [

@@ -60,7 +60,7 @@ static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 // A lean model (the served path) keeps only what prediction needs: the
 // factor regions A, L, Dinv and (mixed precision) the FP64 L^-1 are sized
 // zero here and live in the fit workspace instead (FitLayout).
-static constexpr int kModelRegions = 13;
+static constexpr int kModelRegions = 14;
 static void model_sizes(int64_t M, int precision, bool lean, size_t* sz) {
   const size_t MM = (size_t)M * M;
   const bool mixed = prec_mixed(precision);
@@ -69,7 +69,7 @@ static void model_sizes(int64_t M, int precision, bool lean, size_t* sz) {
                                    lean ? 0 : (size_t)ceil_div(M, kCholNb) * kCholNb * kCholNb * 8, (size_t)M * 8,
                                    (size_t)M * 8, 64,
                                    mixed ? 2 * (size_t)linv_rows((int)M) * linv_pitch((int)M) * 2 : 0,
-                                   (size_t)M * 16, (size_t)pdesc_elems((int)M) * 4};
+                                   (size_t)M * 16, (size_t)pdesc_elems((int)M) * 4, 8 * sizeof(double)};
   for (int r = 0; r < kModelRegions; ++r) sz[r] = v[r];
 }
 
@@ -108,6 +108,7 @@ FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chun
   L.d = take((size_t)M * 8);
   L.ltpart = take((size_t)ceil_div(M, 256) * M * 8);
   L.trws = take(trtri_workspace_elems((int)M) * 8);
+  L.lmlpart = take(kLmlParts * 8);
   if (lean) {
     // A is factored in place (L = A); L^-1 here only for mixed precision
     L.A = take((size_t)M * M * 8);
@@ -210,6 +211,7 @@ gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, bool lean, h
   m->linv_pieces = prec_mixed(prm->precision) ? (__bf16*)take(sizes[10]) : nullptr;
   m->midx = (uint16_t*)take(sizes[11]);
   m->pdesc = (uint32_t*)take(sizes[12]);
+  m->stats = (double*)take(sizes[13]);
   *out = m;
   return GP_OK;
 }
@@ -269,6 +271,8 @@ void enqueue_fit_tail(gp_model* m, const double* x, const double* y, int64_t N, 
   launch_lower_matvec(m->Linv, r, z, M, s);
   launch_lower_t_matvec(m->Linv, z, d, ltpart, M, s);
   launch_axpy(m->w, d, M, s);
+  // y^T y, log det L, sum log Lambda, b^T w and the log marginal likelihood
+  launch_fit_stats(y, N, m->b, m->w, m->L, m->lam, M, m->sigma, (double*)(wb + L.lmlpart), m->stats, s);
   prof_mark(pr, GP_PH_SOLVE, false, s);
   if (prec_mixed(m->precision)) {
     prof_mark(pr, GP_PH_SPLIT, true, s);

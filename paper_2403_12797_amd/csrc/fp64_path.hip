@@ -7,6 +7,7 @@
 //   B (4 x 16):  B[l / 16][l % 16]
 //   D (16 x 16): element q of the lane's double4 is D[4*q + l/16][l % 16]
 #include <stdlib.h>
+#include <utility>
 #include <string.h>
 
 #include "kernels.h"
@@ -274,22 +275,70 @@ __global__ void __launch_bounds__(kPfThreads) potrf_diag_kernel(double* __restri
 
 // The same factor and inverse with two waves.  Lane i of wave H holds
 // row i of the block, columns 32H .. 32H+31, in registers.  Step k: the
-// wave that owns column k takes the pivot sqrt(B[k][k]) from lane k,
-// scales its entry of column k and publishes the column in LDS (two
+// wave that owns column k reads the pivot d = B[k][k] from lane k into
+// scalar registers, forms r = 1/sqrt(d) (hardware estimate and two Newton
+// steps; L[k][k] = d r), scales its entry of column k by r (a product, no
+// division on the step's critical path) and publishes the column in LDS (two
 // alternating buffers, one barrier per step); both waves then subtract
 // l_i l_j from their entries j > k, l_j read back as a broadcast.  Entries
 // above the diagonal collect values that are never used; a failing pivot is
 // recorded and replaced by 1 so the unrolled steps run to the end.  Then
 // X = L^-1 with L in LDS (transposed, so a column is a contiguous row):
 // lane c of wave H forms rows 32H .. 32H+31 of column c by forward
-// substitution, wave 1 after subtracting the contributions of rows 0..31,
-// which wave 0 leaves in LDS.  Rows and columns past the matrix are the
-// identity.
+// substitution (dividing by L[r][r] as a product with the r of step r),
+// wave 1 after subtracting the contributions of rows 0..31, which wave 0
+// leaves in LDS.  Rows and columns past the matrix are the identity.
 constexpr int kPdNone = kNb + 1;
+// Column step K of wave H (both compile-time, so the row stays in registers).
+// 1/sqrt(d) from the hardware estimate and two Newton steps
+// r <- r (3 - d r^2) / 2, each doubling the correct bits.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+  r = r * fma(-0.5 * d * r, r, 1.5);
+  r = r * fma(-0.5 * d * r, r, 1.5);
+  return r;
+}
+
+template <int H, int K>
+__device__ __forceinline__ void potrf_diag2_step(double (&a)[32], int i, double (*colv)[kNb], double* rdiag, int& bad) {
+  if constexpr ((K >> 5) == H) {
+    // pivot B[K][K] from lane K, read into scalar registers
+    const double ak = a[K - 32 * H];
+    const int lo = __builtin_amdgcn_readlane(__double2loint(ak), K);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(ak), K);
+    double d = __hiloint2double(hi, lo);
+    if (!(d > 0.0) || !isfinite(d)) {   // same value in every lane
+      if (!bad) bad = K + 1;
+      d = 1.0;
+    }
+    const double r = rsqrt_nr(d);      // 1 / L[K][K]
+    const double l = i > K ? ak * r : (i == K ? d * r : 0.0);
+    a[K - 32 * H] = l;
+    colv[K & 1][i] = l;
+    if (i == 0) rdiag[K] = r;
+  }
+  __syncthreads();
+  if constexpr (K < 32 * H + 31) {
+    const double li = colv[K & 1][i];
+#pragma unroll
+    for (int jl = 0; jl < 32; ++jl)
+      if (32 * H + jl > K) a[jl] = fma(-li, colv[K & 1][32 * H + jl], a[jl]);
+  }
+  // (the row is pinned here, so the updates stay in their step instead of
+  // being sunk past later barriers with their operands spilled)
+#pragma unroll
+  for (int jl = 0; jl < 32; ++jl) asm volatile("" : "+v"(a[jl]));
+}
+template <int H, int... K>
+__device__ __forceinline__ void potrf_diag2_steps(double (&a)[32], int i, double (*colv)[kNb], double* rdiag,
+                                                  int& bad, std::integer_sequence<int, K...>) {
+  (potrf_diag2_step<H, K>(a, i, colv, rdiag, bad), ...);
+}
+
 template <int H>
 __device__ __forceinline__ void potrf_diag2_body(double* __restrict__ A, int M, int k0, int nb,
                                                  double* __restrict__ Dinv, double (*colv)[kNb], double* Lt,
-                                                 double* Xs, int* sbad) {
+                                                 double* Xs, double* rdiag, int* sbad) {
   const int i = threadIdx.x & 63;
   double a[32];
   // row j of the (symmetric) block, read coalesced: lane i takes B[j][i] = B[i][j]
@@ -299,27 +348,7 @@ __device__ __forceinline__ void potrf_diag2_body(double* __restrict__ A, int M, 
     a[jl] = (i < nb && j < nb) ? A[(int64_t)(k0 + j) * M + k0 + i] : (i == j ? 1.0 : 0.0);
   }
   int bad = 0;
-#pragma unroll
-  for (int k = 0; k < kNb; ++k) {
-    if ((k >> 5) == H) {
-      double d = __shfl(a[k - 32 * H], k);
-      if (!(d > 0.0) || !isfinite(d)) {   // same value in every lane
-        if (!bad) bad = k + 1;
-        d = 1.0;
-      }
-      const double piv = sqrt(d);
-      const double l = i > k ? a[k - 32 * H] / piv : (i == k ? piv : 0.0);
-      a[k - 32 * H] = l;
-      colv[k & 1][i] = l;
-    }
-    __syncthreads();
-    if (k < 32 * H + 31) {
-      const double li = colv[k & 1][i];
-#pragma unroll
-      for (int jl = 0; jl < 32; ++jl)
-        if (32 * H + jl > k) a[jl] = fma(-li, colv[k & 1][32 * H + jl], a[jl]);
-    }
-  }
+  potrf_diag2_steps<H>(a, i, colv, rdiag, bad, std::make_integer_sequence<int, kNb>{});
   if (bad && i == 0) atomicMin(sbad, bad);
 #pragma unroll
   for (int jl = 0; jl < 32; ++jl) {
@@ -342,13 +371,16 @@ __device__ __forceinline__ void potrf_diag2_body(double* __restrict__ A, int M, 
       for (int j = 0; j < 32; ++j) v = fma(-Lt[j * kNbLd + r], Xs[j * kNbLd + i], v);
     }
     x[rl] = v;
+    asm volatile("" : "+v"(x[rl]));
   }
 #pragma unroll
   for (int rl = 0; rl < 32; ++rl) {
     const int r = 32 * H + rl;
-    x[rl] = x[rl] / Lt[r * kNbLd + r];
+    x[rl] = x[rl] * rdiag[r];
 #pragma unroll
     for (int ql = rl + 1; ql < 32; ++ql) x[ql] = fma(-Lt[r * kNbLd + 32 * H + ql], x[rl], x[ql]);
+#pragma unroll
+    for (int ql = 0; ql < 32; ++ql) asm volatile("" : "+v"(x[ql]));
   }
   if (H == 0) {
 #pragma unroll
@@ -368,14 +400,15 @@ __global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A
   __shared__ double colv[2][kNb];
   __shared__ double Lt[kNb * kNbLd];   // Lt[j][i] = L[i][j]
   __shared__ double Xs[32 * kNbLd];    // rows 0..31 of X
+  __shared__ double rdiag[kNb];        // 1 / L[k][k]
   __shared__ int sbad;
   if (*info) return;
   if (threadIdx.x == 0) sbad = kPdNone;
   const int nb = min(kNb, M - k0);
   if ((threadIdx.x >> 6) == 0)
-    potrf_diag2_body<0>(A, M, k0, nb, Dinv, colv, Lt, Xs, &sbad);
+    potrf_diag2_body<0>(A, M, k0, nb, Dinv, colv, Lt, Xs, rdiag, &sbad);
   else
-    potrf_diag2_body<1>(A, M, k0, nb, Dinv, colv, Lt, Xs, &sbad);
+    potrf_diag2_body<1>(A, M, k0, nb, Dinv, colv, Lt, Xs, rdiag, &sbad);
   __syncthreads();
   if (threadIdx.x == 0 && sbad != kPdNone) *info = k0 + sbad;
 }
@@ -437,6 +470,44 @@ __device__ __forceinline__ void tile_gemm64(const double* __restrict__ A, int64_
         for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
     }
   }
+}
+
+// C = alpha A B^T (A: m x k, B: n x k, both row-major; C: m x n, pitch ldc),
+// one 64x64 tile of C per work-group on the pipelined FP64-MFMA tile
+// product.  b_lower: B is lower triangular (B[r][c] = 0 for c > r), so the
+// tile of columns n0.. needs k < n0 + 64 only.
+__global__ void __launch_bounds__(256) gemm_nt_f64_kernel(const double* __restrict__ A, int64_t lda,
+                                                          const double* __restrict__ B, int64_t ldb,
+                                                          double* __restrict__ C, int64_t ldc, int m, int n, int k,
+                                                          double alpha, int b_lower) {
+  __shared__ double As[64 * 17];
+  __shared__ double Bs[16 * 66];
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int ke = b_lower ? min(k, n0 + 64) : k;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  tile_gemm64<true>(A + (int64_t)m0 * lda, lda, B + (int64_t)n0 * ldb, ldb, 0, ke, m - m0, n - n0, k, As, Bs, acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wr = wv >> 1, wc = wv & 1;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = m0 + wr * 32 + a * 16 + 4 * q + (lane >> 4);
+        const int col = n0 + wc * 32 + b * 16 + (lane & 15);
+        if (row < m && col < n) C[(int64_t)row * ldc + col] = alpha * acc[a][b][q];
+      }
+}
+
+void launch_gemm_nt_f64(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, int m,
+                        int n, int k, double alpha, bool b_lower, hipStream_t s) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(gemm_nt_f64_kernel, dim3(ceil_div(n, 64), ceil_div(m, 64)), dim3(256), 0, s, A, lda, B, ldb, C,
+                     ldc, m, n, k, alpha, b_lower ? 1 : 0);
 }
 
 // Panel below the diagonal block: L21 = B21 L11^-T = B21 X^T as one 64x64x64
@@ -506,11 +577,11 @@ __global__ void __launch_bounds__(256) syrk_trailing_kernel(double* __restrict__
       }
 }
 
-// (MGP_CHOL_DIAG=block selects the 512-thread diagonal factor; a tuning
-// knob, the two-wave factor is the default)
+// (MGP_CHOL_DIAG=wave2 selects the two-wave diagonal factor; a tuning knob,
+// the 512-thread factor is the default)
 static bool chol_diag_block() {
   const char* v = getenv("MGP_CHOL_DIAG");
-  return v && strcmp(v, "block") == 0;
+  return !(v && strcmp(v, "wave2") == 0);
 }
 
 void launch_cholesky(double* A, int M, double* Dinv, int* info, hipStream_t s) {

@@ -131,6 +131,19 @@ void launch_midx(int p, int n, int M, uint16_t* midx, hipStream_t s);
 int64_t pdesc_elems(int M);
 void launch_pdesc(int p, int n, int M, uint32_t* pdesc, hipStream_t s);
 
+// C = alpha A B^T (row-major; B lower triangular if b_lower) on FP64 MFMA.
+void launch_gemm_nt_f64(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, int m,
+                        int n, int k, double alpha, bool b_lower, hipStream_t s);
+// Phi_* materialised, row-major [Ns][M] in FP64 (covariance blocks only).
+void launch_phi_dense(const double* xs, int64_t Ns, int p, int n, int M, const double* tab, const uint16_t* midx,
+                      double* out, hipStream_t s);
+// Fit statistics for the log marginal likelihood (see posterior.hip):
+// stats[0] = y^T y, [1] = sum log L_ii, [2] = sum log Lambda_m, [3] = b^T w,
+// [4] = log p(y), [5] = N.  part holds kLmlParts doubles.
+constexpr int kLmlParts = 256;
+void launch_fit_stats(const double* y, int64_t N, const double* b, const double* w, const double* L,
+                      const double* lam, int M, double sigma, double* part, double* stats, hipStream_t s);
+
 // Zero fills as kernels (safe inside captured graphs).
 void launch_fill_zero_int(int* p, int count, hipStream_t s);
 void launch_fill_zero_f64(double* p, int64_t count, hipStream_t s);

@@ -734,8 +734,12 @@ void launch_split_linv(const double* Linv, __bf16* pieces, int M, hipStream_t s)
 // FP64 Phi w kernel.)
 constexpr int kPmTR = 256;
 constexpr int kPmKC = 16;
-constexpr int kPmPitch = kPmKC + 8;     // bf16 per row of a stage buffer (pad against bank conflicts)
 constexpr int kPmThreads = 512;
+// Stage buffers hold 16 columns of R rows per term as [term][column / 8][row][8]:
+// the 8 consecutive columns an MFMA lane reads are one contiguous 16-byte
+// word, and a wave's 64 reads are two contiguous 512-byte runs (no bank
+// conflicts, no padding).
+__host__ __device__ constexpr int pm_at(int q, int R, int x, int c) { return ((q * 2 + (c >> 3)) * R + x) * 8 + (c & 7); }
 
 // distinct prefixes among 16 consecutive columns
 __host__ __device__ inline int pm_pre_rows(int n) { return 15 / n + 2; }
@@ -746,8 +750,8 @@ struct PmCfg {
   static constexpr int WR = 8 / WP;                // waves along r
   static constexpr int CB = kPmTR / WR / 32;       // 32x32 column blocks per wave
   static constexpr int CPT = kPmKC * TN / kPmThreads;  // columns generated per thread per stage
-  static constexpr int PHI = 2 * TN * kPmPitch;    // bf16 in one Phi_* stage buffer
-  static constexpr int LIN = 2 * kPmTR * kPmPitch; // bf16 in one L^-1 stage buffer
+  static constexpr int PHI = 2 * kPmKC * TN;       // bf16 in one Phi_* stage buffer
+  static constexpr int LIN = 2 * kPmKC * kPmTR;    // bf16 in one L^-1 stage buffer
 };
 
 int64_t predict_mixed_part_elems(int64_t Ns, int M, int* groups_out) {
@@ -992,8 +996,8 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     uint32_t hh[C::CPT / 2], ll[C::CPT / 2];
 #pragma unroll
     for (int q = 0; q < C::CPT / 2; ++q) split2(v[2 * q], v[2 * q + 1], hh[q], ll[q]);
-    __bf16* dh = phi + gp * kPmPitch + gq * C::CPT;
-    __bf16* dl = phi + (TN + gp) * kPmPitch + gq * C::CPT;
+    __bf16* dh = phi + pm_at(0, TN, gp, gq * C::CPT);
+    __bf16* dl = phi + pm_at(1, TN, gp, gq * C::CPT);
     if constexpr (C::CPT == 8) {
       *reinterpret_cast<uint4*>(dh) = uint4{hh[0], hh[1], hh[2], hh[3]};
       *reinterpret_cast<uint4*>(dl) = uint4{ll[0], ll[1], ll[2], ll[3]};
@@ -1020,12 +1024,12 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     r0 = *reinterpret_cast<const uint4*>(lbase0 + off);
     r1 = *reinterpret_cast<const uint4*>(lbase1 + off);
   };
-  // thread t stores its two uint4 at (term t >> 9 = 0, row (t >> 1) & 255,
-  // half t & 1) and the same place of term 1
+  // thread t stores its two uint4 at row (t >> 1) & 255, columns 8 (t & 1)
+  // .. +8 of term 0 and the same place of term 1
   auto lin_store = [&](__bf16* lin, const uint4& r0, const uint4& r1) {
     const int r = (t >> 1) & 255, half = t & 1;
-    *reinterpret_cast<uint4*>(lin + r * kPmPitch + half * 8) = r0;
-    *reinterpret_cast<uint4*>(lin + (kPmTR + r) * kPmPitch + half * 8) = r1;
+    *reinterpret_cast<uint4*>(lin + pm_at(0, kPmTR, r, half * 8)) = r0;
+    *reinterpret_cast<uint4*>(lin + pm_at(1, kPmTR, r, half * 8)) = r1;
   };
 
   __syncthreads();  // tables ready
@@ -1092,13 +1096,13 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
 #pragma unroll
         for (int q = 0; q < 2; ++q)
           aop[a][q] = *reinterpret_cast<const bf16x8*>(
-              PHs + (q * TN + wp * 64 + a * 32 + (lane & 31)) * kPmPitch + (lane >> 5) * 8);
+              PHs + pm_at(q, TN, wp * 64 + a * 32 + (lane & 31), (lane >> 5) * 8));
 #pragma unroll
       for (int cb = 0; cb < C::CB; ++cb)
 #pragma unroll
         for (int q = 0; q < 2; ++q)
           bop[cb][q] = *reinterpret_cast<const bf16x8*>(
-              LNs + (q * kPmTR + wr * (kPmTR / C::WR) + cb * 32 + (lane & 31)) * kPmPitch + (lane >> 5) * 8);
+              LNs + pm_at(q, kPmTR, wr * (kPmTR / C::WR) + cb * 32 + (lane & 31), (lane >> 5) * 8));
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll

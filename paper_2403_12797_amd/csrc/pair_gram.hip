@@ -42,7 +42,6 @@ constexpr int kPgT = 256;                      // rows of H per work item
 constexpr int kPgH = 128;                      // columns of H per work item
 constexpr int kPgThreads = 512;
 constexpr int kPgSlots = kPgT + kPgH;          // operand slots per stage
-constexpr int kPgSlotPitch = kGmKC + 8;        // 16-bit elements per slot (16 samples + pad)
 constexpr int kPgTabPitch = kGmKC + 4;         // floats per table / derived row
 constexpr int kPgFlush = 16;                   // stages per MFMA accumulation chain
 constexpr int kPgTop = 7;                      // extra exponent of each group's last dimension
@@ -54,7 +53,14 @@ constexpr int kPgAsmMax = 1024;                // n^p1, n^p2 tabulated by the as
 __host__ __device__ inline int pg_s(int n) { return n * (n + 1) / 2; }
 __host__ __device__ inline int pg_npre1(int p1, int s, int S1) { return p1 > 1 ? (S1 < kPgT ? S1 : kPgT) / s + 2 : 0; }
 __host__ __device__ inline int pg_npre2(int p2, int s, int S2) { return p2 > 1 ? (S2 < kPgH ? S2 : kPgH) / s + 2 : 0; }
-__host__ __device__ constexpr int pg_stage_elems(bool f16) { return (f16 ? 2 : 3) * kPgSlots * kPgSlotPitch; }
+__host__ __device__ constexpr int pg_stage_elems(bool f16) { return (f16 ? 2 : 3) * kPgSlots * kGmKC; }
+// Stage buffers hold 16 samples of each operand slot per term as
+// [term][sample / 8][slot][8]: the 8 consecutive samples an MFMA lane reads
+// are one contiguous 16-byte word, and a wave's 64 reads are two contiguous
+// 512-byte runs.
+__host__ __device__ constexpr int pg_at(int t, int slot, int smp) {
+  return ((t * 2 + (smp >> 3)) * kPgSlots + slot) * 8 + (smp & 7);
+}
 
 // (a, b), a <= b, of pair number t = b(b+1)/2 + a
 __host__ __device__ inline void pg_pair(int t, int& a, int& b) {
@@ -324,7 +330,7 @@ __device__ __forceinline__ void pair_item(unsigned char* smraw, const float* __r
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      E* d = D + (t * kPgSlots + slot) * kPgSlotPitch + s_off;
+      E* d = D + pg_at(t, slot, s_off);
       if constexpr (NS == 8)
         *reinterpret_cast<uint4*>(d) = uint4{w[t][0], w[t][1], w[t][2], w[t][3]};
       else
@@ -407,13 +413,13 @@ __device__ __forceinline__ void pair_item(unsigned char* smraw, const float* __r
 #pragma unroll
       for (int q = 0; q < NT; ++q)
         bop[cb][q] = *reinterpret_cast<const V8*>(
-            S + (q * kPgSlots + kPgT + wc * 64 + cb * 32 + (lane & 31)) * kPgSlotPitch + (lane >> 5) * 8);
+            S + pg_at(q, kPgT + wc * 64 + cb * 32 + (lane & 31), (lane >> 5) * 8));
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
       for (int q = 0; q < NT; ++q)
         aop[rb][q] = *reinterpret_cast<const V8*>(
-            S + (q * kPgSlots + wr * 64 + rb * 32 + (lane & 31)) * kPgSlotPitch + (lane >> 5) * 8);
+            S + pg_at(q, wr * 64 + rb * 32 + (lane & 31), (lane >> 5) * 8));
     auto prod = [&](int qa, int qb) {
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)

@@ -32,6 +32,7 @@ struct gp_model {
   int* flags = nullptr;  // [0] Cholesky info, [1] non-finite input
   uint16_t* midx = nullptr;  // [M][8] multi-index table (1-D table rows per column)
   uint32_t* pdesc = nullptr; // [ceil16(M)] prediction column descriptors
+  double* stats = nullptr;   // [8] fit statistics and log marginal likelihood (launch_fit_stats)
   __bf16* linv_pieces = nullptr;
   bool lean = false;     // keeps only what prediction needs (served models)
   bool charged = false;  // bytes counted in ctx->resident_bytes until freed
@@ -43,7 +44,7 @@ namespace mgp {
 // (byte offsets).  all_splits keeps every Gram partial (no passes).
 struct FitLayout {
   GramPlan g;
-  size_t gpart, tab32, hbuf, vpart, resid, z, r, d, ltpart, trws, total;
+  size_t gpart, tab32, hbuf, vpart, resid, z, r, d, ltpart, trws, lmlpart, total;
   bool lean;
   size_t A, Dinv, Linv;  // lean models only: A (factored in place), Dinv, L^-1 (mixed)
 };
