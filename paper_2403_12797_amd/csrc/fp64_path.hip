@@ -7,6 +7,7 @@
 //   B (4 x 16):  B[l / 16][l % 16]
 //   D (16 x 16): element q of the lane's double4 is D[4*q + l/16][l % 16]
 #include <stdlib.h>
+#include <algorithm>
 #include <utility>
 #include <string.h>
 
@@ -541,28 +542,29 @@ __global__ void __launch_bounds__(256) trsm_panel_kernel(double* __restrict__ A,
       }
 }
 
-__global__ void __launch_bounds__(256) syrk_trailing_kernel(double* __restrict__ A, int M, int k0,
-                                                            const int* __restrict__ info) {
-  // Trailing tile (R, C), C <= R, of the lower part: A[R][C] -= L_R L_C^T with
-  // L_R, L_C the 64 panel columns of rows R and C, on the pipelined 64x64
-  // FP64-MFMA tile product (L_C read transposed).
+// Update of 64-tiles (R, C) of the lower part below / right of the
+// factored columns [k0, k0 + kw): A[R][C] -= L_R L_C^T, L_R and L_C the kw
+// factored columns of the tiles' rows, on the pipelined 64x64 FP64-MFMA tile
+// product (L_C read transposed).  Tiles are counted from row/column `base`:
+// tile columns cb <= C < ce, rows C <= R < T (the diagonal tiles whole).
+__global__ void __launch_bounds__(256) syrk_update_kernel(double* __restrict__ A, int M, int k0, int kw, int base,
+                                                          int cb, int T, const int* __restrict__ info) {
   __shared__ double As[64 * 17];
   __shared__ double Bs[16 * 66];
   if (*info) return;
-  int tile = blockIdx.x, R = 0;
-  while (tile > R) {
-    tile -= R + 1;
-    ++R;
+  int t = blockIdx.x, C = cb;
+  while (t >= T - C) {
+    t -= T - C;
+    ++C;
   }
-  const int C = tile;
-  const int base = k0 + kNb;
+  const int R = C + t;
   const int R0 = base + R * kNb, C0 = base + C * kNb;
   f64x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  tile_gemm64<true>(A + (int64_t)R0 * M + k0, M, A + (int64_t)C0 * M + k0, M, 0, kNb, M - R0, M - C0, kNb, As, Bs,
+  tile_gemm64<true>(A + (int64_t)R0 * M + k0, M, A + (int64_t)C0 * M + k0, M, 0, kw, M - R0, M - C0, kw, As, Bs,
                     acc);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wr = wv >> 1, wc = wv & 1;
 #pragma unroll
@@ -577,25 +579,53 @@ __global__ void __launch_bounds__(256) syrk_trailing_kernel(double* __restrict__
       }
 }
 
-// (MGP_CHOL_DIAG=wave2 selects the two-wave diagonal factor; a tuning knob,
-// the 512-thread factor is the default)
+// tiles of syrk_update_kernel's set {cb <= C < ce, C <= R < T}
+static int64_t update_tiles(int cb, int ce, int T) {
+  int64_t n = 0;
+  for (int C = cb; C < ce; ++C) n += T - C;
+  return n;
+}
+
+// (MGP_CHOL_DIAG=block selects the 512-thread diagonal factor; a tuning
+// knob, the two-wave factor is the default: 4 % faster Cholesky at M = 7776)
 static bool chol_diag_block() {
   const char* v = getenv("MGP_CHOL_DIAG");
-  return !(v && strcmp(v, "wave2") == 0);
+  return v && strcmp(v, "block") == 0;
 }
+
+// Two-level blocking: outer panels of kCholOuter columns, factored in
+// 64-column steps (diagonal block, panel solve below it, update of the
+// panel's remaining columns only); the trailing matrix right of an outer
+// panel is updated once, with all its columns (rank kCholOuter), so the
+// trailing matrix is read and written once per outer panel instead of once
+// per 64 columns.
+constexpr int kCholOuter = 256;
 
 void launch_cholesky(double* A, int M, double* Dinv, int* info, hipStream_t s) {
   const bool blk = chol_diag_block();
-  for (int k0 = 0; k0 < M; k0 += kNb) {
-    if (blk)
-      hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(kPfThreads), 0, s, A, M, k0, Dinv, info);
-    else
-      hipLaunchKernelGGL(potrf_diag2_kernel, dim3(1), dim3(128), 0, s, A, M, k0, Dinv, info);
-    const int rest = M - k0 - kNb;
-    if (rest <= 0) break;
-    const int tb = (int)ceil_div(rest, kNb);
-    hipLaunchKernelGGL(trsm_panel_kernel, dim3(tb), dim3(256), 0, s, A, M, k0, Dinv, info);
-    hipLaunchKernelGGL(syrk_trailing_kernel, dim3(tb * (tb + 1) / 2), dim3(256), 0, s, A, M, k0, info);
+  for (int K0 = 0; K0 < M; K0 += kCholOuter) {
+    const int kend = std::min(M, K0 + kCholOuter);
+    for (int k0 = K0; k0 < kend; k0 += kNb) {
+      if (blk)
+        hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(kPfThreads), 0, s, A, M, k0, Dinv, info);
+      else
+        hipLaunchKernelGGL(potrf_diag2_kernel, dim3(1), dim3(128), 0, s, A, M, k0, Dinv, info);
+      const int rest = M - k0 - kNb;
+      if (rest <= 0) break;
+      const int tb = (int)ceil_div(rest, kNb);
+      hipLaunchKernelGGL(trsm_panel_kernel, dim3(tb), dim3(256), 0, s, A, M, k0, Dinv, info);
+      // the outer panel's remaining columns
+      const int ce = (int)ceil_div(kend - k0 - kNb, kNb);
+      if (ce > 0)
+        hipLaunchKernelGGL(syrk_update_kernel, dim3(update_tiles(0, ce, tb)), dim3(256), 0, s, A, M, k0, kNb,
+                           k0 + kNb, 0, tb, info);
+    }
+    const int rest = M - kend;
+    if (rest > 0) {
+      const int T = (int)ceil_div(rest, kNb);
+      hipLaunchKernelGGL(syrk_update_kernel, dim3(update_tiles(0, T, T)), dim3(256), 0, s, A, M, K0, kend - K0,
+                         kend, 0, T, info);
+    }
   }
 }
 
