@@ -274,23 +274,31 @@ __global__ void __launch_bounds__(kPfThreads) potrf_diag_kernel(double* __restri
   }
 }
 
-// The same factor and inverse with two waves.  Lane i of wave H holds
-// row i of the block, columns 32H .. 32H+31, in registers.  Step k: the
-// wave that owns column k reads the pivot d = B[k][k] from lane k into
-// scalar registers, forms r = 1/sqrt(d) (hardware estimate and two Newton
-// steps; L[k][k] = d r), scales its entry of column k by r (a product, no
-// division on the step's critical path) and publishes the column in LDS (two
-// alternating buffers, one barrier per step); both waves then subtract
-// l_i l_j from their entries j > k, l_j read back as a broadcast.  Entries
-// above the diagonal collect values that are never used; a failing pivot is
-// recorded and replaced by 1 so the unrolled steps run to the end.  Then
-// X = L^-1 with L in LDS (transposed, so a column is a contiguous row):
-// lane c of wave H forms rows 32H .. 32H+31 of column c by forward
-// substitution (dividing by L[r][r] as a product with the r of step r),
-// wave 1 after subtracting the contributions of rows 0..31, which wave 0
-// leaves in LDS.  Rows and columns past the matrix are the identity.
+// The same factor and inverse with two waves.  Lane i of wave H holds row i
+// of the block, columns 32H .. 32H+31, in registers; wave 0 owns columns
+// 0..31 and factors them while wave 1 applies their updates to its columns,
+// then wave 1 factors 32..63.  The owner works in blocks of 8 steps whose
+// body is unrolled, shifting its registers down by 8 after each block, so
+// the pivot column of step 8b + k is always register k.  Step K keeps the
+// pivot chain in registers: column K of L, l (lane i: B[i][K] r with
+// r = 1/sqrt(B[K][K]), L[K][K] = d r, zero above), was formed at the end of
+// the previous step; it is stored in LDS (transposed: Lt[K][i]), column
+// K+1 gets its update from l and l_{K+1} (read from lane K+1), and its
+// pivot is read from lane K+1 and turned into the next l.  Meanwhile every
+// register takes the rank-1 update, l_j read back from LDS (the wave's own
+// writes, in order); registers of columns already factored, or past the
+// wave's columns, collect values that are never read.  The other wave
+// applies a block's 8 updates after the block's barrier.  r comes from the
+// hardware estimate and two Newton steps.  A failing pivot is recorded and
+// replaced by 1 so the loop runs to the end.  Then X = L^-1 by forward
+// substitution in the same pattern, lane c owning column c and wave H rows
+// 32H .. 32H+31: row r is final in register 0.., scaled by 1/L[r][r],
+// stored to LDS and subtracted from the later rows.  L and X leave through
+// LDS.  Rows and columns past the matrix are the identity.
 constexpr int kPdNone = kNb + 1;
-// Column step K of wave H (both compile-time, so the row stays in registers).
+constexpr int kD2Blk = 8;    // steps per unrolled block
+constexpr int kD2Ld = 90;    // Lt pitch: the owner's shifted registers reach column 87
+
 // 1/sqrt(d) from the hardware estimate and two Newton steps
 // r <- r (3 - d r^2) / 2, each doubling the correct bits.
 __device__ __forceinline__ double rsqrt_nr(double d) {
@@ -300,47 +308,35 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
   return r;
 }
 
-template <int H, int K>
-__device__ __forceinline__ void potrf_diag2_step(double (&a)[32], int i, double (*colv)[kNb], double* rdiag, int& bad) {
-  if constexpr ((K >> 5) == H) {
-    // pivot B[K][K] from lane K, read into scalar registers
-    const double ak = a[K - 32 * H];
-    const int lo = __builtin_amdgcn_readlane(__double2loint(ak), K);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(ak), K);
-    double d = __hiloint2double(hi, lo);
-    if (!(d > 0.0) || !isfinite(d)) {   // same value in every lane
-      if (!bad) bad = K + 1;
-      d = 1.0;
-    }
-    const double r = rsqrt_nr(d);      // 1 / L[K][K]
-    const double l = i > K ? ak * r : (i == K ? d * r : 0.0);
-    a[K - 32 * H] = l;
-    colv[K & 1][i] = l;
-    if (i == 0) rdiag[K] = r;
-  }
-  __syncthreads();
-  if constexpr (K < 32 * H + 31) {
-    const double li = colv[K & 1][i];
-#pragma unroll
-    for (int jl = 0; jl < 32; ++jl)
-      if (32 * H + jl > K) a[jl] = fma(-li, colv[K & 1][32 * H + jl], a[jl]);
-  }
-  // (the row is pinned here, so the updates stay in their step instead of
-  // being sunk past later barriers with their operands spilled)
-#pragma unroll
-  for (int jl = 0; jl < 32; ++jl) asm volatile("" : "+v"(a[jl]));
-}
-template <int H, int... K>
-__device__ __forceinline__ void potrf_diag2_steps(double (&a)[32], int i, double (*colv)[kNb], double* rdiag,
-                                                  int& bad, std::integer_sequence<int, K...>) {
-  (potrf_diag2_step<H, K>(a, i, colv, rdiag, bad), ...);
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
 }
 
-template <int H>
-__device__ __forceinline__ void potrf_diag2_body(double* __restrict__ A, int M, int k0, int nb,
-                                                 double* __restrict__ Dinv, double (*colv)[kNb], double* Lt,
-                                                 double* Xs, double* rdiag, int* sbad) {
-  const int i = threadIdx.x & 63;
+// Column `col` of L from the fully updated column c (lane i: B[i][col]):
+// l and rk = 1/L[col][col]; a failing pivot sets bad (1-based) when `real`.
+__device__ __forceinline__ void d2_pivot(double c, int col, int i, bool real, double& l, double& rk, int& bad) {
+  double d = readlane_f64(c, min(col, kNb - 1));   // same value in every lane
+  const bool ok = d > 0.0 && isfinite(d);
+  if (real && !ok && !bad) bad = col + 1;
+  d = ok ? d : 1.0;
+  rk = rsqrt_nr(d);
+  l = i > col ? c * rk : (i == col ? d * rk : 0.0);
+}
+
+__global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A, int M, int k0,
+                                                          double* __restrict__ Dinv, int* __restrict__ info) {
+  __shared__ double Lt[kNb * kD2Ld];   // Lt[j][i] = L[i][j]
+  __shared__ double Xs[kNb * kNb];     // X[r][c]
+  __shared__ double rdiag[kNb];        // 1 / L[k][k]
+  __shared__ int sbad;
+  if (*info) return;
+  const int t = threadIdx.x, i = t & 63;
+  const int H = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int nb = min(kNb, M - k0);
+  for (int e = t; e < kNb * (kD2Ld - kNb); e += 128) Lt[(e / (kD2Ld - kNb)) * kD2Ld + kNb + e % (kD2Ld - kNb)] = 0.0;
+  if (t == 0) sbad = kPdNone;
   double a[32];
   // row j of the (symmetric) block, read coalesced: lane i takes B[j][i] = B[i][j]
 #pragma unroll
@@ -348,70 +344,85 @@ __device__ __forceinline__ void potrf_diag2_body(double* __restrict__ A, int M, 
     const int j = 32 * H + jl;
     a[jl] = (i < nb && j < nb) ? A[(int64_t)(k0 + j) * M + k0 + i] : (i == j ? 1.0 : 0.0);
   }
+  __syncthreads();
   int bad = 0;
-  potrf_diag2_steps<H>(a, i, colv, rdiag, bad, std::make_integer_sequence<int, kNb>{});
-  if (bad && i == 0) atomicMin(sbad, bad);
+  double l = 0.0, rk = 1.0;   // the owner's next column of L and its 1/L[K][K]
+#pragma unroll 1
+  for (int b = 0; b < kNb / kD2Blk; ++b) {
+    const int K0 = kD2Blk * b;
+    if ((b >> 2) == H) {
+      if ((b & 3) == 0) d2_pivot(a[0], K0, i, true, l, rk, bad);
+      const bool last_blk = (b & 3) == 3;
 #pragma unroll
-  for (int jl = 0; jl < 32; ++jl) {
-    const int j = 32 * H + jl;
-    Lt[j * kNbLd + i] = j <= i ? a[jl] : 0.0;
-  }
-  __syncthreads();
-  if (*sbad != kPdNone) return;
-  // L into rows 32H .. 32H+31 of the block (lane i = column; zeros above)
-  for (int r = 32 * H; r < 32 * H + 32 && r < nb; ++r)
-    if (i < nb) A[(int64_t)(k0 + r) * M + k0 + i] = Lt[i * kNbLd + r];
-  double x[32];
-  if (H == 1) __syncthreads();   // rows 0..31 of X are in Xs
+      for (int kl = 0; kl < kD2Blk; ++kl) {
+        const int K = K0 + kl;
+        Lt[K * kD2Ld + i] = l;
+        rdiag[K] = rk;
+        __builtin_amdgcn_wave_barrier();
+        const double c = fma(-l, readlane_f64(l, min(K + 1, kNb - 1)), a[kl + 1]);
+        const double* lr = Lt + K * kD2Ld + K0;   // register jl holds column K0 + jl
 #pragma unroll
-  for (int rl = 0; rl < 32; ++rl) {
-    const int r = 32 * H + rl;
-    double v = r == i ? 1.0 : 0.0;
-    if (H == 1) {
+        for (int jl = 0; jl < 32; ++jl) a[jl] = fma(-l, lr[jl], a[jl]);
+        d2_pivot(c, K + 1, i, kl + 1 < kD2Blk || !last_blk, l, rk, bad);
+      }
 #pragma unroll
-      for (int j = 0; j < 32; ++j) v = fma(-Lt[j * kNbLd + r], Xs[j * kNbLd + i], v);
+      for (int j = 0; j < 32 - kD2Blk; ++j) a[j] = a[j + kD2Blk];
     }
-    x[rl] = v;
-    asm volatile("" : "+v"(x[rl]));
-  }
-#pragma unroll
-  for (int rl = 0; rl < 32; ++rl) {
-    const int r = 32 * H + rl;
-    x[rl] = x[rl] * rdiag[r];
-#pragma unroll
-    for (int ql = rl + 1; ql < 32; ++ql) x[ql] = fma(-Lt[r * kNbLd + 32 * H + ql], x[rl], x[ql]);
-#pragma unroll
-    for (int ql = 0; ql < 32; ++ql) asm volatile("" : "+v"(x[ql]));
-  }
-  if (H == 0) {
-#pragma unroll
-    for (int rl = 0; rl < 32; ++rl) Xs[rl * kNbLd + i] = x[rl];
     __syncthreads();
-  }
-  double* D = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
+    if ((b >> 2) < H) {
 #pragma unroll
-  for (int rl = 0; rl < 32; ++rl) {
-    const int r = 32 * H + rl;
-    D[r * kNb + i] = (r < nb && i < nb && i <= r) ? x[rl] : 0.0;
+      for (int kl = 0; kl < kD2Blk; ++kl) {
+        const int K = K0 + kl;
+        const double li = Lt[K * kD2Ld + i];
+        const double* lr = Lt + K * kD2Ld + 32 * H;
+#pragma unroll
+        for (int jl = 0; jl < 32; ++jl) a[jl] = fma(-li, lr[jl], a[jl]);
+      }
+    }
   }
-}
-
-__global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A, int M, int k0,
-                                                          double* __restrict__ Dinv, int* __restrict__ info) {
-  __shared__ double colv[2][kNb];
-  __shared__ double Lt[kNb * kNbLd];   // Lt[j][i] = L[i][j]
-  __shared__ double Xs[32 * kNbLd];    // rows 0..31 of X
-  __shared__ double rdiag[kNb];        // 1 / L[k][k]
-  __shared__ int sbad;
-  if (*info) return;
-  if (threadIdx.x == 0) sbad = kPdNone;
-  const int nb = min(kNb, M - k0);
-  if ((threadIdx.x >> 6) == 0)
-    potrf_diag2_body<0>(A, M, k0, nb, Dinv, colv, Lt, Xs, rdiag, &sbad);
-  else
-    potrf_diag2_body<1>(A, M, k0, nb, Dinv, colv, Lt, Xs, rdiag, &sbad);
+  if (bad && i == 0) atomicMin(&sbad, bad);
   __syncthreads();
-  if (threadIdx.x == 0 && sbad != kPdNone) *info = k0 + sbad;
+  if (sbad != kPdNone) {
+    if (t == 0) *info = k0 + sbad;
+    return;
+  }
+  double x[32];   // rows 32H + q of X (shifted like a), column i
+#pragma unroll
+  for (int q = 0; q < 32; ++q) x[q] = 32 * H + q == i ? 1.0 : 0.0;
+#pragma unroll 1
+  for (int b = 0; b < kNb / kD2Blk; ++b) {
+    const int R0 = kD2Blk * b;
+    if ((b >> 2) == H) {
+#pragma unroll
+      for (int rl = 0; rl < kD2Blk; ++rl) {
+        const int r = R0 + rl;
+        const double xr = x[rl] * rdiag[r];
+        Xs[r * kNb + i] = xr;
+        const double* lr = Lt + r * kD2Ld + R0;   // L[R0 + q][r]
+#pragma unroll
+        for (int q = 0; q < 32; ++q) x[q] = fma(-lr[q], xr, x[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 32 - kD2Blk; ++q) x[q] = x[q + kD2Blk];
+    }
+    __syncthreads();
+    if ((b >> 2) < H) {
+#pragma unroll
+      for (int rl = 0; rl < kD2Blk; ++rl) {
+        const int r = R0 + rl;
+        const double xr = Xs[r * kNb + i];
+        const double* lr = Lt + r * kD2Ld + 32 * H;   // L[32H + q][r]
+#pragma unroll
+        for (int q = 0; q < 32; ++q) x[q] = fma(-lr[q], xr, x[q]);
+      }
+    }
+  }
+  // L (zeros above the diagonal) and X, each wave every other row, lane i = column
+  double* D = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
+  for (int r = H; r < kNb; r += 2) {
+    if (r < nb && i < nb) A[(int64_t)(k0 + r) * M + k0 + i] = Lt[i * kD2Ld + r];
+    D[r * kNb + i] = (r < nb && i < nb && i <= r) ? Xs[r * kNb + i] : 0.0;
+  }
 }
 
 // One 64x64 output tile of C = sum_k A[m][k] B[k][n] with A, B row-major in

@@ -3,14 +3,16 @@
 // A scheduler thread per context admits queued requests as soon as a stream
 // slot is free and the request's device footprint fits what the context's
 // HBM budget has left, enqueues its fit and/or predict on that slot's stream
-// (so the work of admitted requests overlaps on the GPU), and retires
-// requests whose completion event has fired.  Admission scans the queue in
+// (so the work of admitted requests overlaps on the GPU; the enqueue runs
+// without the context lock), and retires requests whose completion event
+// has fired.  The number of slots follows the budget (slot_count).  Admission scans the queue in
 // arrival order and takes the first request that fits; a request that does
 // not fit is passed over at most kMaxBypass times, after which admission
 // waits for it (no request starves behind a stream of smaller ones).
 // Fitted models are lean (w, the tables and the variance factor) and stay
 // device-resident; a model handed to the caller keeps its bytes charged to
 // the budget until it is freed.
+#include <algorithm>
 #include <chrono>
 #include <stdlib.h>
 #include <string.h>
@@ -19,7 +21,17 @@
 
 namespace mgp {
 
-constexpr int kSlots = 4;
+// Stream slots: MGP_SLOTS if set (1..16), else one per 32 GiB of the HBM
+// budget, between 4 and 8.
+constexpr int kMinSlots = 4, kMaxSlots = 8;
+static int slot_count(size_t budget) {
+  if (const char* v = getenv("MGP_SLOTS")) {
+    const int k = atoi(v);
+    if (k >= 1 && k <= 16) return k;
+  }
+  const int64_t k = (int64_t)(budget >> 35);
+  return (int)std::max<int64_t>(kMinSlots, std::min<int64_t>(kMaxSlots, k));
+}
 constexpr int kMaxBypass = 32;
 
 static double now_s() {
@@ -57,42 +69,51 @@ static void finish(gp_ctx* ctx, Request* r, gp_status st) {
   }
 }
 
-// Allocate and enqueue one admitted request on slot k (mu held).
-static void launch(gp_ctx* ctx, Request* r, int k) {
+// Allocate and enqueue one admitted request on slot k.  Called with lk
+// held; the slot is reserved for r, and the allocations and the (many)
+// kernel launches of the request are made with the lock released, so
+// gp_submit and gp_poll are not held up meanwhile (only this thread touches
+// the slots).
+static void launch(gp_ctx* ctx, Request* r, int k, std::unique_lock<std::mutex>& lk) {
   Slot& sl = ctx->slots[k];
   const gp_request& d = r->desc;
   r->slot = k;
+  sl.req = r;
+  lk.unlock();
+  gp_status st = GP_OK;
   hipError_t e = hipMallocAsync(&r->ws, r->ws_bytes ? r->ws_bytes : 256, sl.stream);
   if (e != hipSuccess) {
     r->ws = nullptr;
-    finish(ctx, r, GP_ENOMEM);
-    return;
+    st = GP_ENOMEM;
   }
   const gp_model* pm = d.model;
-  if (d.kind != GP_REQ_PREDICT) {
+  if (st == GP_OK && d.kind != GP_REQ_PREDICT) {
     gp_params prm = d.params;
     prm.eps = r->eps;
     prm.alpha = r->alpha;
     int64_t M = 0;
     validate_params(&prm, &M);
-    gp_status st = model_alloc(ctx, &prm, M, true, sl.stream, &r->model);
-    if (st != GP_OK) {
-      finish(ctx, r, st);
-      return;
+    st = model_alloc(ctx, &prm, M, true, sl.stream, &r->model);
+    if (st == GP_OK) {
+      enqueue_fit(r->model, d.x, d.y, d.N, r->layout, r->ws, sl.stream);
+      hipMemcpyAsync(sl.flags_host, r->model->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, sl.stream);
+      pm = r->model;
     }
-    enqueue_fit(r->model, d.x, d.y, d.N, r->layout, r->ws, sl.stream);
-    hipMemcpyAsync(sl.flags_host, r->model->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, sl.stream);
-    pm = r->model;
-  } else {
+  } else if (st == GP_OK) {
     sl.flags_host[0] = sl.flags_host[1] = 0;
   }
-  if (d.kind != GP_REQ_FIT && d.Ns > 0 && (d.mean || d.var)) {
+  if (st == GP_OK && d.kind != GP_REQ_FIT && d.Ns > 0 && (d.mean || d.var)) {
     // predict workspace follows the fit workspace in the same block
     enqueue_predict(pm, d.xs, d.Ns, d.mean, d.var, (char*)r->ws + r->fit_ws_bytes, sl.stream);
   }
-  hipEventRecord(sl.done, sl.stream);
+  if (st == GP_OK) hipEventRecord(sl.done, sl.stream);
+  lk.lock();
+  if (st != GP_OK) {
+    sl.req = nullptr;
+    finish(ctx, r, st);
+    return;
+  }
   r->t_admit = now_s();
-  sl.req = r;
 }
 
 static void scheduler_loop(gp_ctx* ctx) {
@@ -146,9 +167,12 @@ static void scheduler_loop(gp_ctx* ctx) {
         if (it != ctx->queue.begin()) ctx->queue.front()->bypassed += 1;
         it = ctx->queue.erase(it);
         ctx->in_flight_bytes += r->footprint;
-        launch(ctx, r, free_slot);
+        launch(ctx, r, free_slot, lk);
         if (r->status != GP_PENDING) ctx->cv_done.notify_all();
         else ++active;
+        // gp_submit may have appended while the lock was released, which
+        // invalidates deque iterators: rescan from the head
+        it = ctx->queue.begin();
         continue;
       }
       // r waits for memory; later requests may pass it until the head has
@@ -168,7 +192,7 @@ static void scheduler_loop(gp_ctx* ctx) {
 }
 
 gp_status scheduler_start(gp_ctx* ctx) {
-  ctx->slots.resize(kSlots);
+  ctx->slots.resize(slot_count(ctx->budget));
   for (auto& sl : ctx->slots) {
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
