@@ -967,14 +967,25 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   // consecutive last-factor rows (CPT-aligned groups never cross a prefix),
   // so one descriptor serves the group.  (Columns past M generate finite
   // values that meet the zero columns of the padded L^-1.)
-  auto gen_read = [&](int k, const float* pre, float* ga, float* gb) {
+  // The descriptors of a stage are loaded one stage before they are used,
+  // by a vector load (lane u takes the stage's descriptor u), and moved to
+  // scalar registers when used: a scalar load would share the wait counter
+  // of the LDS operand reads and hold up the MFMAs until it returned.
+  constexpr int ND = G ? 1 : C::CPT;
+  auto load_desc = [&](int k) {
     const int c0 = __builtin_amdgcn_readfirstlane(k * kPmKC + gq * C::CPT);
-    const uint2* dsc = pdesc + c0;
+    return pdesc[c0 + (lane & (C::CPT - 1))];   // c0 + CPT - 1 < ceil16(M)
+  };
+  auto take_desc = [&](const uint2& dv, uint2* d) {
+#pragma unroll
+    for (int u = 0; u < ND; ++u)
+      d[u] = uint2{(uint32_t)__builtin_amdgcn_readlane((int)dv.x, u), (uint32_t)__builtin_amdgcn_readlane((int)dv.y, u)};
+  };
+  auto gen_read = [&](const uint2* d, const float* pre, float* ga, float* gb) {
     const char* pre_gp = reinterpret_cast<const char*>(pre + gp);
     if constexpr (G) {
-      const uint2 d = dsc[0];
-      const float pv = *reinterpret_cast<const float*>(pre_gp + d.x);
-      const float* lp = reinterpret_cast<const float*>(tf_gp + d.y);
+      const float pv = *reinterpret_cast<const float*>(pre_gp + d[0].x);
+      const float* lp = reinterpret_cast<const float*>(tf_gp + d[0].y);
 #pragma unroll
       for (int u = 0; u < C::CPT; ++u) {
         ga[u] = pv;
@@ -983,9 +994,8 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     } else {
 #pragma unroll
       for (int u = 0; u < C::CPT; ++u) {
-        const uint2 d = dsc[u];
-        ga[u] = *reinterpret_cast<const float*>(pre_gp + d.x);
-        gb[u] = *reinterpret_cast<const float*>(tf_gp + d.y);
+        ga[u] = *reinterpret_cast<const float*>(pre_gp + d[u].x);
+        gb[u] = *reinterpret_cast<const float*>(tf_gp + d[u].y);
       }
     }
   };
@@ -1007,8 +1017,10 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     }
   };
   auto gen = [&](int k, const float* pre, __bf16* phi) {
+    uint2 d[ND];
+    take_desc(load_desc(k), d);
     float ga[C::CPT], gb[C::CPT];
-    gen_read(k, pre, ga, gb);
+    gen_read(d, pre, ga, gb);
     gen_store(ga, gb, phi);
   };
   // L^-1 slab (rows r0..r0+255, columns c0..c0+15, both terms): 1024 uint4,
@@ -1063,7 +1075,12 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     __syncthreads();
     gen(s0.k, pre0, buf0);
     lin_store(buf0 + C::PHI, la0, la1);
+    // (loads in the steady state's order: slab of s1, descriptors of s1,
+    // slab of s2)
     lin_load(s1.rb, s1.k, lb0, lb1);
+    __builtin_amdgcn_sched_barrier(0);
+    uint2 dcur = load_desc(s1.k);   // descriptors of stage s1 (lane u: descriptor u)
+    __builtin_amdgcn_sched_barrier(0);
     lin_load(s2.rb, s2.k, la0, la1);
     if (s1.rb < rb1) make_pre(s1.k, pre0 + npr * TN);
     __syncthreads();
@@ -1086,8 +1103,13 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     auto stage = [&](uint4& R0, uint4& R1) __attribute__((always_inline)) {
       const bool pre_next = s2.rb < rb1;
       float* const pdst = pre0 + (pb ^ 1) * npr * TN;
+      const uint2 dnext = load_desc(s2.k);
       float ga[C::CPT], gb[C::CPT];
-      gen_read(s1.k, pre0 + pb * npr * TN, ga, gb);
+      {
+        uint2 d[ND];
+        take_desc(dcur, d);
+        gen_read(d, pre0 + pb * npr * TN, ga, gb);
+      }
       const __bf16* PHs = buf0 + b * (C::PHI + C::LIN);
       const __bf16* LNs = PHs + C::PHI;
       bf16x8 aop[2][2], bop[C::CB][2];
@@ -1149,6 +1171,7 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
       s1 = s2;
       s2 = s3;
       adv(s3);
+      dcur = dnext;
     };
     // stages alternate the two slab registers
     for (int q = 0; q + 1 < S; q += 2) {
