@@ -359,11 +359,39 @@ __global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A
         Lt[K * kD2Ld + i] = l;
         rdiag[K] = rk;
         __builtin_amdgcn_wave_barrier();
-        const double c = fma(-l, readlane_f64(l, min(K + 1, kNb - 1)), a[kl + 1]);
         const double* lr = Lt + K * kD2Ld + K0;   // register jl holds column K0 + jl
+        double lv[32];
 #pragma unroll
-        for (int jl = 0; jl < 32; ++jl) a[jl] = fma(-l, lr[jl], a[jl]);
-        d2_pivot(c, K + 1, i, kl + 1 < kD2Blk || !last_blk, l, rk, bad);
+        for (int jl = 0; jl < 32; ++jl) lv[jl] = lr[jl];
+        // the pivot chain of the next column in segments, each followed by a
+        // quarter of the rank-1 update, so that its latency hides under them
+        const double c = fma(-l, readlane_f64(l, min(K + 1, kNb - 1)), a[kl + 1]);
+        double d = readlane_f64(c, min(K + 1, kNb - 1));
+        const bool ok = d > 0.0 && isfinite(d);
+        if ((kl + 1 < kD2Blk || !last_blk) && !ok && !bad) bad = K + 2;
+        d = ok ? d : 1.0;
+        double r = __builtin_amdgcn_rsq(d);
+        const double hd = -0.5 * d;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int jl = 0; jl < 8; ++jl) a[jl] = fma(-l, lv[jl], a[jl]);
+        __builtin_amdgcn_sched_barrier(0);
+        r = r * fma(hd * r, r, 1.5);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int jl = 8; jl < 16; ++jl) a[jl] = fma(-l, lv[jl], a[jl]);
+        __builtin_amdgcn_sched_barrier(0);
+        r = r * fma(hd * r, r, 1.5);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int jl = 16; jl < 24; ++jl) a[jl] = fma(-l, lv[jl], a[jl]);
+        __builtin_amdgcn_sched_barrier(0);
+        const double ln = i > K + 1 ? c * r : (i == K + 1 ? d * r : 0.0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int jl = 24; jl < 32; ++jl) a[jl] = fma(-l, lv[jl], a[jl]);
+        l = ln;
+        rk = r;
       }
 #pragma unroll
       for (int j = 0; j < 32 - kD2Blk; ++j) a[j] = a[j + kD2Blk];
