@@ -834,7 +834,7 @@ template <int TN, int P, bool G, int SCH = 0>
 __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     const double* __restrict__ xs, int64_t Ns, int n, int M, const double* __restrict__ tab,
     const uint16_t* __restrict__ midx, const uint32_t* __restrict__ pdesc_words, const __bf16* __restrict__ lpieces,
-    int rpg, double* __restrict__ part) {
+    int groups, double* __restrict__ part) {
   const uint2* __restrict__ pdesc = reinterpret_cast<const uint2*>(pdesc_words);
   using C = PmCfg<TN>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smraw[];
@@ -847,7 +847,26 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   const int npd = pm_pdig_entries(P, n, M);
   const int64_t i0 = (int64_t)blockIdx.x * TN;
   const int RB = (M + kPmTR - 1) / kPmTR;
-  const int rb0 = blockIdx.y * rpg, rb1 = min(rb0 + rpg, RB);
+  // Row blocks [rb0, rb1) of this group: the groups split the column stages
+  // evenly (row block rb has min((rb + 1) * 16, ceil(M / 16)) of them, the
+  // triangle of L^-1), not the row blocks, which would leave the last group
+  // with most of the work.
+  int rb0 = RB, rb1 = RB;
+  {
+    const int mcs = (M + kPmKC - 1) / kPmKC;
+    int total = 0;
+    for (int r = 0; r < RB; ++r) total += min((r + 1) * (kPmTR / kPmKC), mcs);
+    const int g = blockIdx.y;
+    int cum = 0;
+    for (int r = 0; r < RB; ++r) {
+      if (rb0 == RB && cum * groups >= g * total) rb0 = r;
+      if (cum * groups >= (g + 1) * total) {
+        rb1 = r;
+        break;
+      }
+      cum += min((r + 1) * (kPmTR / kPmKC), mcs);
+    }
+  }
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wp = wv % C::WP, wr = wv / C::WP;
   const int LP = linv_pitch(M);
@@ -1274,13 +1293,12 @@ void launch_predict_mixed(const double* xs, int64_t Ns, int p, int n, int M, con
   int want = (int)ceil_div(1024, ib);
   if (want > groups) want = groups;
   if (want < 1) want = 1;
-  const int rpg = (int)ceil_div(RB, want);
-  groups = (int)ceil_div(RB, rpg);
+  groups = want < RB ? want : RB;
   prof_mark(prof, GP_PH_PREDICT, true, s);
   const bool G = n % (kPmKC * TN / kPmThreads) == 0;
   predict_kernel_for(TN, p, G)<<<dim3(ib, groups), dim3(kPmThreads), TN == 256 ? predict_lds_bytes<256>(p, n)
                                                                              : predict_lds_bytes<128>(p, n), s>>>(
-      xs, Ns, n, M, tab, midx, pdesc, linv_pieces, rpg, part);
+      xs, Ns, n, M, tab, midx, pdesc, linv_pieces, groups, part);
   prof_mark(prof, GP_PH_PREDICT, false, s);
   prof_mark(prof, GP_PH_PREDICT_REDUCE, true, s);
   hipLaunchKernelGGL(predict_mixed_reduce_kernel, dim3(ceil_div(Ns, 256)), dim3(256), 0, s, part, groups, Ns,

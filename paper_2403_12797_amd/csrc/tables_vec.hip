@@ -241,11 +241,18 @@ void launch_phi_matvec(const double* x, int64_t N, int p, int n, int M, const do
 // where PRE is the product of the leading p-1 factors, so
 //   (Phi^T v)[hi*n + k] = sum_i PRE[i][hi] * (phi_{p-1,k}(x_i) v_i),
 // an (M/n x N) by (N x n) product.  Work-group: 256 prefixes hi x all n
-// last digits over a chunk of kTvChunk samples, FP64 MFMA (16x16x4) on
-// per-stage tiles of 16 samples built in LDS: PRE^T [16 samples][256 hi]
-// and W [16 samples][n padded to 16].  Partials part[chunk][M] are reduced
-// in chunk order.
-constexpr int kTvChunk = 1024;
+// last digits over a chunk of samples, FP64 MFMA (16x16x4) on per-stage
+// tiles of 16 samples built in LDS: PRE^T [16 samples][256 hi] and
+// W [16 samples][n padded to 16]; the samples (x, v) of the next stage are
+// loaded while the current one is processed.  The chunk (a multiple of 16,
+// 64 .. 1024) is sized so that about 256 work-groups share the samples: a
+// small problem is not left to a few work-groups walking long chunks.
+// Partials part[chunk][M] are reduced in chunk order.
+constexpr int kTvChunkMax = 1024;
+static int64_t phiT_chunk(int64_t N) {
+  int64_t c = (ceil_div(N, 256) + 15) / 16 * 16;
+  return c < 64 ? 64 : c > kTvChunkMax ? kTvChunkMax : c;
+}
 constexpr int kTvKC = 16;
 constexpr int kTvLd = kTvKC + 1;     // table row pitch: rows of consecutive digits hit distinct LDS banks
 constexpr int kTvH = 256;
@@ -254,22 +261,23 @@ __device__ __forceinline__ f64x4 mfma64v(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-int64_t phiT_part_elems(int64_t N, int M) { return ceil_div(N, kTvChunk) * (int64_t)M; }
+int64_t phiT_part_elems(int64_t N, int M) { return ceil_div(N, phiT_chunk(N)) * (int64_t)M; }
 
 template <int NB>   // NB = ceil(n / 16) column blocks of the last digit
 __global__ void __launch_bounds__(256) phiT_gemm_kernel(const double* __restrict__ x, const double* __restrict__ v,
-                                                        int64_t N, int p, int n, int M,
+                                                        int64_t N, int p, int n, int M, int64_t chunk,
                                                         const double* __restrict__ tab, double* __restrict__ part) {
   extern __shared__ double sm[];
   double* T = sm;                                 // [p*n][17] 1-D tables of the stage
   double* PR = T + p * n * kTvLd;                 // [16][kTvH + 2]
   double* W = PR + kTvKC * (kTvH + 2);            // [16][NB*16 + 2]
+  double* VS = W + kTvKC * (NB * 16 + 2);         // [16] v of the stage
   const int WP = NB * 16 + 2;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int H = M / n;
   const int h0 = blockIdx.y * kTvH;
-  const int64_t c0 = (int64_t)blockIdx.x * kTvChunk;
-  const int64_t c1 = min(c0 + kTvChunk, N);
+  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const int64_t c1 = min(c0 + chunk, N);
   // prefix digits of this thread's hi (one per thread)
   const int hi = h0 + t;
   int dig[GP_MAX_P];
@@ -290,20 +298,29 @@ __global__ void __launch_bounds__(256) phiT_gemm_kernel(const double* __restrict
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
 
+  // the stage's samples: thread (i, j), i < 16, j < p, holds x[s0 + i][j];
+  // thread i < 16 holds v[s0 + i]
+  const int xi = t % kTvKC, xj = t / kTvKC;
+  auto load_x = [&](int64_t s) { return (xj < p && s + xi < c1) ? x[(s + xi) * p + xj] : 0.0; };
+  auto load_v = [&](int64_t s) { return (t < kTvKC && s + t < c1) ? v[s + t] : 0.0; };
+  double xn = load_x(c0), vn = load_v(c0);
   for (int64_t s0 = c0; s0 < c1; s0 += kTvKC) {
+    const double xc = xn, vc = vn;
+    xn = load_x(s0 + kTvKC);
+    vn = load_v(s0 + kTvKC);
     __syncthreads();
     // 1-D tables: thread (i, j) for i < 16, j < p
-    if (t < kTvKC * p) {
-      const int i = t % kTvKC, j = t / kTvKC;
-      const int64_t row = s0 + i;
-      double* o = T + (j * n) * kTvLd + i;
+    if (xj < p) {
+      const int64_t row = s0 + xi;
+      double* o = T + (xj * n) * kTvLd + xi;
       if (row < c1) {
-        const double* dc = tab + kTabDim + j * kDimStride;
-        phi_1d<double, double>(x[row * p + j], dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, kTvLd);
+        const double* dc = tab + kTabDim + xj * kDimStride;
+        phi_1d<double, double>(xc, dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, kTvLd);
       } else {
         for (int k = 0; k < n; ++k) o[k * kTvLd] = 0.0;
       }
     }
+    if (t < kTvKC) VS[t] = vc;
     __syncthreads();
     // PRE^T: thread = prefix, 16 samples (one unrolled body per factor count)
     {
@@ -336,7 +353,7 @@ __global__ void __launch_bounds__(256) phiT_gemm_kernel(const double* __restrict
     for (int u = t; u < kTvKC * NB * 16; u += 256) {
       const int i = u / (NB * 16), k = u % (NB * 16);
       const int64_t row = s0 + i;
-      W[i * WP + k] = (k < n && row < c1) ? T[((p - 1) * n + k) * kTvLd + i] * v[row] : 0.0;
+      W[i * WP + k] = (k < n && row < c1) ? T[((p - 1) * n + k) * kTvLd + i] * VS[i] : 0.0;
     }
     __syncthreads();
     // MFMA: wave wv owns prefixes wv*64 .. +64 (4 blocks of 16)
@@ -381,16 +398,18 @@ __global__ void reduce_cols_kernel(const double* __restrict__ part, int64_t chun
 
 void launch_phiT_vec(const double* x, const double* v, int64_t N, int p, int n, int M, const double* tab,
                      double* part, const double* sub, const double* wsub, double* out, hipStream_t s) {
-  const int64_t chunks = ceil_div(N, kTvChunk);
+  const int64_t chunk = phiT_chunk(N);
+  const int64_t chunks = ceil_div(N, chunk);
   const int H = M / n;
   const int NB = (int)ceil_div(n, 16);
-  const size_t lds = (size_t)(p * n * kTvLd + kTvKC * (kTvH + 2) + kTvKC * (NB * 16 + 2)) * sizeof(double);
+  const size_t lds =
+      (size_t)(p * n * kTvLd + kTvKC * (kTvH + 2) + kTvKC * (NB * 16 + 2) + kTvKC) * sizeof(double);
   const dim3 grid(chunks, ceil_div(H, kTvH));
   switch (NB) {
-    case 1: hipLaunchKernelGGL(phiT_gemm_kernel<1>, grid, dim3(256), lds, s, x, v, N, p, n, M, tab, part); break;
-    case 2: hipLaunchKernelGGL(phiT_gemm_kernel<2>, grid, dim3(256), lds, s, x, v, N, p, n, M, tab, part); break;
-    case 3: hipLaunchKernelGGL(phiT_gemm_kernel<3>, grid, dim3(256), lds, s, x, v, N, p, n, M, tab, part); break;
-    default: hipLaunchKernelGGL(phiT_gemm_kernel<4>, grid, dim3(256), lds, s, x, v, N, p, n, M, tab, part); break;
+    case 1: hipLaunchKernelGGL(phiT_gemm_kernel<1>, grid, dim3(256), lds, s, x, v, N, p, n, M, chunk, tab, part); break;
+    case 2: hipLaunchKernelGGL(phiT_gemm_kernel<2>, grid, dim3(256), lds, s, x, v, N, p, n, M, chunk, tab, part); break;
+    case 3: hipLaunchKernelGGL(phiT_gemm_kernel<3>, grid, dim3(256), lds, s, x, v, N, p, n, M, chunk, tab, part); break;
+    default: hipLaunchKernelGGL(phiT_gemm_kernel<4>, grid, dim3(256), lds, s, x, v, N, p, n, M, chunk, tab, part); break;
   }
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part, chunks, M, sub, wsub, out);
 }
