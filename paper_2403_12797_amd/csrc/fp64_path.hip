@@ -285,9 +285,10 @@ __global__ void __launch_bounds__(kPfThreads) potrf_diag_kernel(double* __restri
 // the previous step; it is stored in LDS (transposed: Lt[K][i]), column
 // K+1 gets its update from l and l_{K+1} (read from lane K+1), and its
 // pivot is read from lane K+1 and turned into the next l.  Meanwhile every
-// register takes the rank-1 update, l_j read back from LDS (the wave's own
-// writes, in order); registers of columns already factored, or past the
-// wave's columns, collect values that are never read.  The other wave
+// register takes the rank-1 update of the previous step, l_j read back from
+// LDS (the wave's own writes, in order, stored a step earlier), so the LDS
+// round trip stays off the pivot chain; registers of columns already
+// factored, or past the wave's columns, collect values that are never read.  The other wave
 // applies a block's 8 updates after the block's barrier.  r comes from the
 // hardware estimate and two Newton steps.  A failing pivot is recorded and
 // replaced by 1 so the loop runs to the end.  Then X = L^-1 by forward
@@ -347,25 +348,43 @@ __global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A
   __syncthreads();
   int bad = 0;
   double l = 0.0, rk = 1.0;   // the owner's next column of L and its 1/L[K][K]
+  double lp = 0.0;            // the owner's previous column, whose rank-1 update is pending
 #pragma unroll 1
   for (int b = 0; b < kNb / kD2Blk; ++b) {
     const int K0 = kD2Blk * b;
     if ((b >> 2) == H) {
-      if ((b & 3) == 0) d2_pivot(a[0], K0, i, true, l, rk, bad);
+      const bool first_blk = (b & 3) == 0;
+      if (first_blk) {
+        d2_pivot(a[0], K0, i, true, l, rk, bad);
+        lp = 0.0;
+      }
       const bool last_blk = (b & 3) == 3;
 #pragma unroll
       for (int kl = 0; kl < kD2Blk; ++kl) {
         const int K = K0 + kl;
         Lt[K * kD2Ld + i] = l;
         rdiag[K] = rk;
-        __builtin_amdgcn_wave_barrier();
-        const double* lr = Lt + K * kD2Ld + K0;   // register jl holds column K0 + jl
+        // The rank-1 update of step K is applied one step late, from the row
+        // stored a step earlier (its LDS round trip off the pivot chain); the
+        // next column takes the pending update and this step's from lanes
+        // K + 1 of lp and l, in the same order.  Register jl holds column
+        // K0 + jl (after a block's shift the pending row lines up with the
+        // next block's columns).  The first step of the wave has none pending.
+        const bool pend = kl > 0 || !first_blk;
         double lv[32];
+        if (pend) {
+          const double* lr = Lt + (K - 1) * kD2Ld + K0;
 #pragma unroll
-        for (int jl = 0; jl < 32; ++jl) lv[jl] = lr[jl];
+          for (int jl = 0; jl < 32; ++jl) lv[jl] = lr[jl];
+        } else {
+#pragma unroll
+          for (int jl = 0; jl < 32; ++jl) lv[jl] = 0.0;
+        }
         // the pivot chain of the next column in segments, each followed by a
-        // quarter of the rank-1 update, so that its latency hides under them
-        const double c = fma(-l, readlane_f64(l, min(K + 1, kNb - 1)), a[kl + 1]);
+        // quarter of the pending rank-1 update, so that its latency hides
+        // under them
+        const int k1 = min(K + 1, kNb - 1);
+        const double c = fma(-l, readlane_f64(l, k1), fma(-lp, readlane_f64(lp, k1), a[kl + 1]));
         double d = readlane_f64(c, min(K + 1, kNb - 1));
         const bool ok = d > 0.0 && isfinite(d);
         if ((kl + 1 < kD2Blk || !last_blk) && !ok && !bad) bad = K + 2;
@@ -374,22 +393,23 @@ __global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A
         const double hd = -0.5 * d;
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int jl = 0; jl < 8; ++jl) a[jl] = fma(-l, lv[jl], a[jl]);
+        for (int jl = 0; jl < 8; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
         __builtin_amdgcn_sched_barrier(0);
         r = r * fma(hd * r, r, 1.5);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int jl = 8; jl < 16; ++jl) a[jl] = fma(-l, lv[jl], a[jl]);
+        for (int jl = 8; jl < 16; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
         __builtin_amdgcn_sched_barrier(0);
         r = r * fma(hd * r, r, 1.5);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int jl = 16; jl < 24; ++jl) a[jl] = fma(-l, lv[jl], a[jl]);
+        for (int jl = 16; jl < 24; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
         __builtin_amdgcn_sched_barrier(0);
         const double ln = i > K + 1 ? c * r : (i == K + 1 ? d * r : 0.0);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int jl = 24; jl < 32; ++jl) a[jl] = fma(-l, lv[jl], a[jl]);
+        for (int jl = 24; jl < 32; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
+        lp = l;
         l = ln;
         rk = r;
       }
@@ -421,14 +441,29 @@ __global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A
   for (int b = 0; b < kNb / kD2Blk; ++b) {
     const int R0 = kD2Blk * b;
     if ((b >> 2) == H) {
+      // (L and its diagonal are final: the block's 1/L[r][r] and each next
+      // row are read ahead of their step)
+      double rdv[kD2Blk], lc[32];
+#pragma unroll
+      for (int rl = 0; rl < kD2Blk; ++rl) rdv[rl] = rdiag[R0 + rl];
+#pragma unroll
+      for (int q = 0; q < 32; ++q) lc[q] = Lt[R0 * kD2Ld + R0 + q];
 #pragma unroll
       for (int rl = 0; rl < kD2Blk; ++rl) {
         const int r = R0 + rl;
-        const double xr = x[rl] * rdiag[r];
-        Xs[r * kNb + i] = xr;
-        const double* lr = Lt + r * kD2Ld + R0;   // L[R0 + q][r]
+        double ln[32];
+        if (rl + 1 < kD2Blk) {
 #pragma unroll
-        for (int q = 0; q < 32; ++q) x[q] = fma(-lr[q], xr, x[q]);
+          for (int q = 0; q < 32; ++q) ln[q] = Lt[(r + 1) * kD2Ld + R0 + q];   // L[R0 + q][r + 1]
+        }
+        const double xr = x[rl] * rdv[rl];
+        Xs[r * kNb + i] = xr;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) x[q] = fma(-lc[q], xr, x[q]);   // L[R0 + q][r]
+        if (rl + 1 < kD2Blk) {
+#pragma unroll
+          for (int q = 0; q < 32; ++q) lc[q] = ln[q];
+        }
       }
 #pragma unroll
       for (int q = 0; q < 32 - kD2Blk; ++q) x[q] = x[q + kD2Blk];
