@@ -274,31 +274,35 @@ __global__ void __launch_bounds__(kPfThreads) potrf_diag_kernel(double* __restri
   }
 }
 
-// The same factor and inverse with two waves.  Lane i of wave H holds row i
-// of the block, columns 32H .. 32H+31, in registers; wave 0 owns columns
-// 0..31 and factors them while wave 1 applies their updates to its columns,
-// then wave 1 factors 32..63.  The owner works in blocks of 8 steps whose
-// body is unrolled, shifting its registers down by 8 after each block, so
-// the pivot column of step 8b + k is always register k.  Step K keeps the
-// pivot chain in registers: column K of L, l (lane i: B[i][K] r with
-// r = 1/sqrt(B[K][K]), L[K][K] = d r, zero above), was formed at the end of
-// the previous step; it is stored in LDS (transposed: Lt[K][i]), column
-// K+1 gets its update from l and l_{K+1} (read from lane K+1), and its
-// pivot is read from lane K+1 and turned into the next l.  Meanwhile every
-// register takes the rank-1 update of the previous step, l_j read back from
-// LDS (the wave's own writes, in order, stored a step earlier), so the LDS
-// round trip stays off the pivot chain; registers of columns already
-// factored, or past the wave's columns, collect values that are never read.  The other wave
-// applies a block's 8 updates after the block's barrier.  r comes from the
-// hardware estimate and two Newton steps.  A failing pivot is recorded and
-// replaced by 1 so the loop runs to the end.  Then X = L^-1 by forward
-// substitution in the same pattern, lane c owning column c and wave H rows
-// 32H .. 32H+31: row r is final in register 0.., scaled by 1/L[r][r],
-// stored to LDS and subtracted from the later rows.  L and X leave through
-// LDS.  Rows and columns past the matrix are the identity.
+// The same factor and inverse with W waves (4 by default, 2 behind a knob).
+// Lane i of wave H holds row i of the block, columns C H .. C H + C - 1
+// (C = 64 / W), in registers; wave H owns those columns and factors them
+// while the waves right of it apply their updates to their own columns.
+// The owner works in blocks of 8 steps whose body is unrolled, shifting its
+// registers down by 8 after each block, so the pivot column of step 8b + k
+// is always register k.  Step K keeps the pivot chain in registers: column
+// K of L, l (lane i: B[i][K] r with r = 1/sqrt(B[K][K]), L[K][K] = d r, zero
+// above), was formed at the end of the previous step; it is stored in LDS
+// (transposed: Lt[K][i]), column K+1 gets its update from l and l_{K+1}
+// (read from lane K+1), and its pivot is read from lane K+1 and turned into
+// the next l.  Meanwhile every register takes the rank-1 update of the
+// previous step, l_j read back from LDS (the wave's own writes, in order,
+// stored a step earlier), so the LDS round trip stays off the pivot chain;
+// registers of columns already factored, or past the wave's columns,
+// collect values that are never read.  The waves right of the owner apply a
+// block's 8 updates after the block's barrier.  r comes from the hardware
+// estimate and two Newton steps.  A failing pivot is recorded and replaced
+// by 1 so the loop runs to the end.  Then X = L^-1 by forward substitution
+// in the same pattern, lane c owning column c and wave H rows C H ..
+// C H + C - 1: row r is final in register 0 of its owner, scaled by
+// 1/L[r][r], stored to LDS and subtracted from the later rows.  L and X
+// leave through LDS.  Rows and columns past the matrix are the identity.
 constexpr int kPdNone = kNb + 1;
 constexpr int kD2Blk = 8;    // steps per unrolled block
-constexpr int kD2Ld = 90;    // Lt pitch: the owner's shifted registers reach column 87
+// Lt pitch for W waves of 64 / W columns: the owner's shifted registers reach
+// column 56 + 64 / W - 1; even (16-byte rows), 2 * pitch = 4 mod 8 words
+// (transposed reads at most 4-way bank conflicts)
+template <int W> constexpr int kD2Ld = W == 2 ? 90 : 74;
 
 // 1/sqrt(d) from the hardware estimate and two Newton steps
 // r <- r (3 - d r^2) / 2, each doubling the correct bits.
@@ -326,9 +330,14 @@ __device__ __forceinline__ void d2_pivot(double c, int col, int i, bool real, do
   l = i > col ? c * rk : (i == col ? d * rk : 0.0);
 }
 
-__global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A, int M, int k0,
-                                                          double* __restrict__ Dinv, int* __restrict__ info) {
-  __shared__ double Lt[kNb * kD2Ld];   // Lt[j][i] = L[i][j]
+template <int W>
+__global__ void __launch_bounds__(64 * W) potrf_diag2_kernel(double* __restrict__ A, int M, int k0,
+                                                             double* __restrict__ Dinv, int* __restrict__ info) {
+  constexpr int C = kNb / W;          // columns (rows in the inverse) per wave
+  constexpr int BPW = C / kD2Blk;     // 8-step blocks per wave
+  constexpr int Ld = kD2Ld<W>;
+  static_assert(C % kD2Blk == 0 && C % 4 == 0, "wave columns");
+  __shared__ double Lt[kNb * Ld];   // Lt[j][i] = L[i][j]
   __shared__ double Xs[kNb * kNb];     // X[r][c]
   __shared__ double rdiag[kNb];        // 1 / L[k][k]
   __shared__ int sbad;
@@ -336,13 +345,13 @@ __global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A
   const int t = threadIdx.x, i = t & 63;
   const int H = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nb = min(kNb, M - k0);
-  for (int e = t; e < kNb * (kD2Ld - kNb); e += 128) Lt[(e / (kD2Ld - kNb)) * kD2Ld + kNb + e % (kD2Ld - kNb)] = 0.0;
+  for (int e = t; e < kNb * (Ld - kNb); e += 64 * W) Lt[(e / (Ld - kNb)) * Ld + kNb + e % (Ld - kNb)] = 0.0;
   if (t == 0) sbad = kPdNone;
-  double a[32];
+  double a[C];
   // row j of the (symmetric) block, read coalesced: lane i takes B[j][i] = B[i][j]
 #pragma unroll
-  for (int jl = 0; jl < 32; ++jl) {
-    const int j = 32 * H + jl;
+  for (int jl = 0; jl < C; ++jl) {
+    const int j = C * H + jl;
     a[jl] = (i < nb && j < nb) ? A[(int64_t)(k0 + j) * M + k0 + i] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
@@ -352,17 +361,17 @@ __global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A
 #pragma unroll 1
   for (int b = 0; b < kNb / kD2Blk; ++b) {
     const int K0 = kD2Blk * b;
-    if ((b >> 2) == H) {
-      const bool first_blk = (b & 3) == 0;
+    if (b / BPW == H) {
+      const bool first_blk = b % BPW == 0;
       if (first_blk) {
         d2_pivot(a[0], K0, i, true, l, rk, bad);
         lp = 0.0;
       }
-      const bool last_blk = (b & 3) == 3;
+      const bool last_blk = b % BPW == BPW - 1;
 #pragma unroll
       for (int kl = 0; kl < kD2Blk; ++kl) {
         const int K = K0 + kl;
-        Lt[K * kD2Ld + i] = l;
+        Lt[K * Ld + i] = l;
         rdiag[K] = rk;
         // The rank-1 update of step K is applied one step late, from the row
         // stored a step earlier (its LDS round trip off the pivot chain); the
@@ -371,14 +380,14 @@ __global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A
         // K0 + jl (after a block's shift the pending row lines up with the
         // next block's columns).  The first step of the wave has none pending.
         const bool pend = kl > 0 || !first_blk;
-        double lv[32];
+        double lv[C];
         if (pend) {
-          const double* lr = Lt + (K - 1) * kD2Ld + K0;
+          const double* lr = Lt + (K - 1) * Ld + K0;
 #pragma unroll
-          for (int jl = 0; jl < 32; ++jl) lv[jl] = lr[jl];
+          for (int jl = 0; jl < C; ++jl) lv[jl] = lr[jl];
         } else {
 #pragma unroll
-          for (int jl = 0; jl < 32; ++jl) lv[jl] = 0.0;
+          for (int jl = 0; jl < C; ++jl) lv[jl] = 0.0;
         }
         // the pivot chain of the next column in segments, each followed by a
         // quarter of the pending rank-1 update, so that its latency hides
@@ -393,38 +402,38 @@ __global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A
         const double hd = -0.5 * d;
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int jl = 0; jl < 8; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
+        for (int jl = 0; jl < C / 4; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
         __builtin_amdgcn_sched_barrier(0);
         r = r * fma(hd * r, r, 1.5);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int jl = 8; jl < 16; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
+        for (int jl = C / 4; jl < C / 2; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
         __builtin_amdgcn_sched_barrier(0);
         r = r * fma(hd * r, r, 1.5);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int jl = 16; jl < 24; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
+        for (int jl = C / 2; jl < 3 * C / 4; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
         __builtin_amdgcn_sched_barrier(0);
         const double ln = i > K + 1 ? c * r : (i == K + 1 ? d * r : 0.0);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int jl = 24; jl < 32; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
+        for (int jl = 3 * C / 4; jl < C; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
         lp = l;
         l = ln;
         rk = r;
       }
 #pragma unroll
-      for (int j = 0; j < 32 - kD2Blk; ++j) a[j] = a[j + kD2Blk];
+      for (int j = 0; j < C - kD2Blk; ++j) a[j] = a[j + kD2Blk];
     }
     __syncthreads();
-    if ((b >> 2) < H) {
+    if (b / BPW < H) {
 #pragma unroll
       for (int kl = 0; kl < kD2Blk; ++kl) {
         const int K = K0 + kl;
-        const double li = Lt[K * kD2Ld + i];
-        const double* lr = Lt + K * kD2Ld + 32 * H;
+        const double li = Lt[K * Ld + i];
+        const double* lr = Lt + K * Ld + C * H;
 #pragma unroll
-        for (int jl = 0; jl < 32; ++jl) a[jl] = fma(-li, lr[jl], a[jl]);
+        for (int jl = 0; jl < C; ++jl) a[jl] = fma(-li, lr[jl], a[jl]);
       }
     }
   }
@@ -434,56 +443,56 @@ __global__ void __launch_bounds__(128) potrf_diag2_kernel(double* __restrict__ A
     if (t == 0) *info = k0 + sbad;
     return;
   }
-  double x[32];   // rows 32H + q of X (shifted like a), column i
+  double x[C];   // rows C H + q of X (shifted like a), column i
 #pragma unroll
-  for (int q = 0; q < 32; ++q) x[q] = 32 * H + q == i ? 1.0 : 0.0;
+  for (int q = 0; q < C; ++q) x[q] = C * H + q == i ? 1.0 : 0.0;
 #pragma unroll 1
   for (int b = 0; b < kNb / kD2Blk; ++b) {
     const int R0 = kD2Blk * b;
-    if ((b >> 2) == H) {
+    if (b / BPW == H) {
       // (L and its diagonal are final: the block's 1/L[r][r] and each next
       // row are read ahead of their step)
-      double rdv[kD2Blk], lc[32];
+      double rdv[kD2Blk], lc[C];
 #pragma unroll
       for (int rl = 0; rl < kD2Blk; ++rl) rdv[rl] = rdiag[R0 + rl];
 #pragma unroll
-      for (int q = 0; q < 32; ++q) lc[q] = Lt[R0 * kD2Ld + R0 + q];
+      for (int q = 0; q < C; ++q) lc[q] = Lt[R0 * Ld + R0 + q];
 #pragma unroll
       for (int rl = 0; rl < kD2Blk; ++rl) {
         const int r = R0 + rl;
-        double ln[32];
+        double ln[C];
         if (rl + 1 < kD2Blk) {
 #pragma unroll
-          for (int q = 0; q < 32; ++q) ln[q] = Lt[(r + 1) * kD2Ld + R0 + q];   // L[R0 + q][r + 1]
+          for (int q = 0; q < C; ++q) ln[q] = Lt[(r + 1) * Ld + R0 + q];   // L[R0 + q][r + 1]
         }
         const double xr = x[rl] * rdv[rl];
         Xs[r * kNb + i] = xr;
 #pragma unroll
-        for (int q = 0; q < 32; ++q) x[q] = fma(-lc[q], xr, x[q]);   // L[R0 + q][r]
+        for (int q = 0; q < C; ++q) x[q] = fma(-lc[q], xr, x[q]);   // L[R0 + q][r]
         if (rl + 1 < kD2Blk) {
 #pragma unroll
-          for (int q = 0; q < 32; ++q) lc[q] = ln[q];
+          for (int q = 0; q < C; ++q) lc[q] = ln[q];
         }
       }
 #pragma unroll
-      for (int q = 0; q < 32 - kD2Blk; ++q) x[q] = x[q + kD2Blk];
+      for (int q = 0; q < C - kD2Blk; ++q) x[q] = x[q + kD2Blk];
     }
     __syncthreads();
-    if ((b >> 2) < H) {
+    if (b / BPW < H) {
 #pragma unroll
       for (int rl = 0; rl < kD2Blk; ++rl) {
         const int r = R0 + rl;
         const double xr = Xs[r * kNb + i];
-        const double* lr = Lt + r * kD2Ld + 32 * H;   // L[32H + q][r]
+        const double* lr = Lt + r * Ld + C * H;   // L[C H + q][r]
 #pragma unroll
-        for (int q = 0; q < 32; ++q) x[q] = fma(-lr[q], xr, x[q]);
+        for (int q = 0; q < C; ++q) x[q] = fma(-lr[q], xr, x[q]);
       }
     }
   }
   // L (zeros above the diagonal) and X, each wave every other row, lane i = column
   double* D = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
-  for (int r = H; r < kNb; r += 2) {
-    if (r < nb && i < nb) A[(int64_t)(k0 + r) * M + k0 + i] = Lt[i * kD2Ld + r];
+  for (int r = H; r < kNb; r += W) {
+    if (r < nb && i < nb) A[(int64_t)(k0 + r) * M + k0 + i] = Lt[i * Ld + r];
     D[r * kNb + i] = (r < nb && i < nb && i <= r) ? Xs[r * kNb + i] : 0.0;
   }
 }
@@ -660,6 +669,19 @@ static int64_t update_tiles(int cb, int ce, int T) {
   return n;
 }
 
+// The two-wave-pattern diagonal factor on MGP_CHOL_W waves (2 or 4; a
+// tuning knob, default 4).
+static int chol_waves() {
+  const char* v = getenv("MGP_CHOL_W");
+  return v && atoi(v) == 2 ? 2 : 4;
+}
+static void launch_diag2(double* A, int M, int k0, double* Dinv, int* info, hipStream_t s) {
+  if (chol_waves() == 2)
+    hipLaunchKernelGGL(potrf_diag2_kernel<2>, dim3(1), dim3(128), 0, s, A, M, k0, Dinv, info);
+  else
+    hipLaunchKernelGGL(potrf_diag2_kernel<4>, dim3(1), dim3(256), 0, s, A, M, k0, Dinv, info);
+}
+
 // (MGP_CHOL_DIAG=block selects the 512-thread diagonal factor; a tuning
 // knob, the two-wave factor is the default: 4 % faster Cholesky at M = 7776)
 static bool chol_diag_block() {
@@ -683,7 +705,7 @@ void launch_cholesky(double* A, int M, double* Dinv, int* info, hipStream_t s) {
       if (blk)
         hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(kPfThreads), 0, s, A, M, k0, Dinv, info);
       else
-        hipLaunchKernelGGL(potrf_diag2_kernel, dim3(1), dim3(128), 0, s, A, M, k0, Dinv, info);
+        launch_diag2(A, M, k0, Dinv, info, s);
       const int rest = M - k0 - kNb;
       if (rest <= 0) break;
       const int tb = (int)ceil_div(rest, kNb);
