@@ -261,7 +261,14 @@ __device__ __forceinline__ f64x4 mfma64v(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-int64_t phiT_part_elems(int64_t N, int M) { return ceil_div(N, phiT_chunk(N)) * (int64_t)M; }
+// Partials are reduced in two passes: kTvGroups groups of consecutive
+// chunks (one work-group column each), then the group sums in order.
+constexpr int64_t kTvGroups = 64;
+static int64_t phiT_groups(int64_t chunks) { return chunks < kTvGroups ? chunks : kTvGroups; }
+int64_t phiT_part_elems(int64_t N, int M) {
+  const int64_t chunks = ceil_div(N, phiT_chunk(N));
+  return (chunks + phiT_groups(chunks)) * (int64_t)M;
+}
 
 template <int NB>   // NB = ceil(n / 16) column blocks of the last digit
 __global__ void __launch_bounds__(256) phiT_gemm_kernel(const double* __restrict__ x, const double* __restrict__ v,
@@ -385,13 +392,24 @@ __global__ void __launch_bounds__(256) phiT_gemm_kernel(const double* __restrict
       }
 }
 
-__global__ void reduce_cols_kernel(const double* __restrict__ part, int64_t chunks, int M,
+// Group g of G sums the chunks [g*per, (g+1)*per) of column m in order into
+// row chunks + g of part; then the G group rows are summed in order.
+__global__ void reduce_cols_group_kernel(double* __restrict__ part, int64_t chunks, int64_t per, int M) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const int64_t c0 = (int64_t)blockIdx.y * per, c1 = min(c0 + per, chunks);
+  double s = 0.0;
+  for (int64_t c = c0; c < c1; ++c) s += part[c * M + m];
+  part[(chunks + blockIdx.y) * M + m] = s;
+}
+
+__global__ void reduce_cols_kernel(const double* __restrict__ part, int64_t rows, int M,
                                    const double* __restrict__ sub, const double* __restrict__ wsub,
                                    double* __restrict__ out) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
   double s = 0.0;
-  for (int64_t c = 0; c < chunks; ++c) s += part[c * M + m];
+  for (int64_t c = 0; c < rows; ++c) s += part[c * M + m];
   if (sub) s -= sub[m] * wsub[m];
   out[m] = s;
 }
@@ -411,7 +429,11 @@ void launch_phiT_vec(const double* x, const double* v, int64_t N, int p, int n, 
     case 3: hipLaunchKernelGGL(phiT_gemm_kernel<3>, grid, dim3(256), lds, s, x, v, N, p, n, M, chunk, tab, part); break;
     default: hipLaunchKernelGGL(phiT_gemm_kernel<4>, grid, dim3(256), lds, s, x, v, N, p, n, M, chunk, tab, part); break;
   }
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part, chunks, M, sub, wsub, out);
+  const int64_t G = phiT_groups(chunks), per = ceil_div(chunks, G);
+  hipLaunchKernelGGL(reduce_cols_group_kernel, dim3(ceil_div(M, 256), ceil_div(chunks, per)), dim3(256), 0, s, part,
+                     chunks, per, M);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part + chunks * (int64_t)M,
+                     ceil_div(chunks, per), M, sub, wsub, out);
 }
 
 // ---------------------------------------------------------------- input checks
