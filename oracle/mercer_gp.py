@@ -23,6 +23,18 @@ displays in order:
 The paper's global scale factor rho is called ``alpha`` here (one per input
 dimension, as in (19)-(20)); its length scale is ``eps``.
 
+Other Mercer kernels (Sec. 2.3 notes that expansions exist for kernels other
+than the SE, e.g. periodic ones, without giving them).  ``kernel="periodic"``
+selects the periodic (exp-sine-squared) kernel, per input dimension
+    k(x, x') = exp(-2 eps^2 sin^2(alpha (x - x') / 2)),
+period 2 pi / alpha, length scale 1 / eps.  With a = eps^2 and
+2 sin^2(u/2) = 1 - cos u, the Jacobi-Anger expansion
+exp(a cos u) = I_0(a) + 2 sum_{k>=1} I_k(a) cos(k u) gives its exact Mercer
+expansion on one period (uniform measure): eigenfunctions 1, sqrt(2) cos(k alpha x),
+sqrt(2) sin(k alpha x) (orthonormal), eigenvalues e^-a I_0(a), then
+e^-a I_k(a) twice (cos and sin).  Truncation to n columns per dimension and
+the tensor product over dimensions (eqs. (18)-(20)) are as for the SE.
+
 Readings where the paper is garbled or silent (each one pinned by a test):
   * delta^2 in (14) prints as rho/2 (beta^2 - 1); the Fasshauer-McCourt value
     rho^2/2 (beta^2 - 1) is used.  Only that value makes the eigenfunctions
@@ -55,11 +67,14 @@ import scipy.linalg as sla
 
 __all__ = [
     "se_scalars", "gamma_coeffs", "eigenvalues_1d", "hermite_physicists",
-    "eigenfunctions_1d", "multi_indices", "eigenvalues_nd", "eigenfunctions_nd",
-    "se_ard_kernel", "truncated_kernel", "Fit", "fit", "predict", "predict_cov",
+    "eigenfunctions_1d", "periodic_eigenvalues_1d", "periodic_eigenfunctions_1d",
+    "multi_indices", "eigenvalues_nd", "eigenfunctions_nd",
+    "se_ard_kernel", "periodic_ard_kernel", "truncated_kernel", "Fit", "fit", "predict", "predict_cov",
     "log_marginal_likelihood", "log_marginal_likelihood_nxn",
-    "posterior_woodbury_W", "posterior_truncated_nxn", "posterior_exact_se",
+    "posterior_woodbury_W", "posterior_truncated_nxn", "posterior_exact_se", "posterior_exact",
 ]
+
+KERNELS = ("se", "periodic")
 
 
 def _as_dim_array(v, p):
@@ -128,6 +143,50 @@ def eigenfunctions_1d(x: np.ndarray, eps: float, alpha: float, n: int) -> np.nda
 
 
 # --------------------------------------------------------------------------
+# 1-D periodic eigenpairs (Jacobi-Anger; see the module docstring)
+# --------------------------------------------------------------------------
+def periodic_eigenvalues_1d(eps: float, n: int) -> np.ndarray:
+    """lambda_1 = e^-a I_0(a); lambda_{2k} = lambda_{2k+1} = e^-a I_k(a),
+    a = eps^2 (scipy's exponentially scaled Bessel function ive)."""
+    from scipy.special import ive
+    a = eps * eps
+    k = (np.arange(n) + 1) // 2
+    return ive(k, a)
+
+
+def periodic_eigenfunctions_1d(x: np.ndarray, eps: float, alpha: float, n: int) -> np.ndarray:
+    """phi_1 = 1, phi_{2k} = sqrt(2) cos(k alpha x), phi_{2k+1} = sqrt(2) sin(k alpha x).
+    x: any shape; returns x.shape + (n,), column i-1 holding phi_i."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.empty(x.shape + (n,), dtype=np.float64)
+    for c in range(n):
+        k = (c + 1) // 2
+        if c == 0:
+            out[..., c] = 1.0
+        elif c % 2 == 1:
+            out[..., c] = math.sqrt(2.0) * np.cos(k * alpha * x)
+        else:
+            out[..., c] = math.sqrt(2.0) * np.sin(k * alpha * x)
+    return out
+
+
+def _eigvals_1d(kernel, eps, alpha, n):
+    if kernel == "se":
+        return eigenvalues_1d(eps, alpha, n)
+    if kernel == "periodic":
+        return periodic_eigenvalues_1d(eps, n)
+    raise ValueError(f"unknown kernel {kernel!r}")
+
+
+def _eigfuns_1d(kernel, x, eps, alpha, n):
+    if kernel == "se":
+        return eigenfunctions_1d(x, eps, alpha, n)
+    if kernel == "periodic":
+        return periodic_eigenfunctions_1d(x, eps, alpha, n)
+    raise ValueError(f"unknown kernel {kernel!r}")
+
+
+# --------------------------------------------------------------------------
 # p-variate tensor-product expansion, Sec. 2.3 eqs. (17)-(20)
 # --------------------------------------------------------------------------
 def multi_indices(n: int, p: int) -> np.ndarray:
@@ -137,19 +196,20 @@ def multi_indices(n: int, p: int) -> np.ndarray:
     return np.stack([g.reshape(-1) for g in grids], axis=1)
 
 
-def eigenvalues_nd(eps, alpha, n: int, p: int, order: np.ndarray | None = None) -> np.ndarray:
+def eigenvalues_nd(eps, alpha, n: int, p: int, order: np.ndarray | None = None,
+                   kernel: str = "se") -> np.ndarray:
     """Lambda_m = prod_j lambda_{k_j(m)}(eps_j, alpha_j), eq. (20)."""
     eps = _as_dim_array(eps, p)
     alpha = _as_dim_array(alpha, p)
     idx = multi_indices(n, p) if order is None else order
     lam = np.ones(idx.shape[0])
     for j in range(p):
-        lam = lam * eigenvalues_1d(eps[j], alpha[j], n)[idx[:, j]]
+        lam = lam * _eigvals_1d(kernel, eps[j], alpha[j], n)[idx[:, j]]
     return lam
 
 
 def eigenfunctions_nd(X: np.ndarray, eps, alpha, n: int,
-                      order: np.ndarray | None = None) -> np.ndarray:
+                      order: np.ndarray | None = None, kernel: str = "se") -> np.ndarray:
     """Phi[i, m] = prod_j phi_{k_j(m)}(x_ij; eps_j, alpha_j), eq. (19).
     X: (N, p).  Returns (N, n^p)."""
     X = np.atleast_2d(np.asarray(X, dtype=np.float64))
@@ -159,7 +219,7 @@ def eigenfunctions_nd(X: np.ndarray, eps, alpha, n: int,
     idx = multi_indices(n, p) if order is None else order
     Phi = np.ones((X.shape[0], idx.shape[0]))
     for j in range(p):
-        phij = eigenfunctions_1d(X[:, j], eps[j], alpha[j], n)
+        phij = _eigfuns_1d(kernel, X[:, j], eps[j], alpha[j], n)
         Phi *= phij[:, idx[:, j]]
     return Phi
 
@@ -175,12 +235,28 @@ def se_ard_kernel(X1: np.ndarray, X2: np.ndarray, eps) -> np.ndarray:
     return np.exp(-d2)
 
 
-def truncated_kernel(X1, X2, eps, alpha, n: int) -> np.ndarray:
+def periodic_ard_kernel(X1: np.ndarray, X2: np.ndarray, eps, alpha) -> np.ndarray:
+    """Closed-form product periodic kernel:
+    prod_j exp(-2 eps_j^2 sin^2(alpha_j (x_j - x'_j) / 2))."""
+    X1 = np.atleast_2d(np.asarray(X1, dtype=np.float64))
+    X2 = np.atleast_2d(np.asarray(X2, dtype=np.float64))
+    p = X1.shape[1]
+    eps = _as_dim_array(eps, p)
+    alpha = _as_dim_array(alpha, p)
+    e = np.zeros((X1.shape[0], X2.shape[0]))
+    for j in range(p):
+        s = np.sin(alpha[j] * (X1[:, j][:, None] - X2[:, j][None, :]) / 2.0)
+        e += 2.0 * eps[j] ** 2 * s * s
+    return np.exp(-e)
+
+
+def truncated_kernel(X1, X2, eps, alpha, n: int, kernel: str = "se") -> np.ndarray:
     """Phi(X1) Lambda Phi(X2)^T, eq. (7) with the expansion (18)."""
     X1 = np.atleast_2d(X1)
     p = X1.shape[1]
-    lam = eigenvalues_nd(eps, alpha, n, p)
-    return (eigenfunctions_nd(X1, eps, alpha, n) * lam) @ eigenfunctions_nd(X2, eps, alpha, n).T
+    lam = eigenvalues_nd(eps, alpha, n, p, kernel=kernel)
+    return (eigenfunctions_nd(X1, eps, alpha, n, kernel=kernel) * lam) @ \
+        eigenfunctions_nd(X2, eps, alpha, n, kernel=kernel).T
 
 
 # --------------------------------------------------------------------------
@@ -199,10 +275,11 @@ class Fit:
     lu: tuple                # LU factorisation of A (scipy lu_factor)
     w: np.ndarray            # (M,)  A^-1 Phi^T y  (C-order multi-index)
     order: np.ndarray | None = None   # multi-index table if not C order
+    kernel: str = "se"                # "se" (eqs. 13-20) or "periodic"
 
 
 def fit(X, y, sigma: float, eps, alpha, n: int, chunk: int = 8192,
-        order: np.ndarray | None = None) -> Fit:
+        order: np.ndarray | None = None, kernel: str = "se") -> Fit:
     """Weight-space fit.  A = sigma^2 Lambda_bar with Lambda_bar of (10);
     the Gram Phi^T Phi and Phi^T y are summed over row blocks of `chunk`
     samples in natural order (only to bound memory: Phi itself is N x n^p).
@@ -215,18 +292,18 @@ def fit(X, y, sigma: float, eps, alpha, n: int, chunk: int = 8192,
         raise ValueError("x and y disagree on N")
     eps = _as_dim_array(eps, p)
     alpha = _as_dim_array(alpha, p)
-    lam = eigenvalues_nd(eps, alpha, n, p, order)
+    lam = eigenvalues_nd(eps, alpha, n, p, order, kernel=kernel)
     M = lam.shape[0]
     G = np.zeros((M, M))
     b = np.zeros(M)
     for s in range(0, N, chunk):
-        Phi = eigenfunctions_nd(X[s:s + chunk], eps, alpha, n, order)
+        Phi = eigenfunctions_nd(X[s:s + chunk], eps, alpha, n, order, kernel=kernel)
         G += Phi.T @ Phi
         b += Phi.T @ y[s:s + chunk]
     A = G + np.diag(sigma * sigma / lam)
     lu = sla.lu_factor(A)
     w = sla.lu_solve(lu, b)
-    return Fit(p, n, float(sigma), eps, alpha, lam, A, b, lu, w, order)
+    return Fit(p, n, float(sigma), eps, alpha, lam, A, b, lu, w, order, kernel)
 
 
 def predict(f: Fit, Xs, chunk: int = 4096):
@@ -236,7 +313,7 @@ def predict(f: Fit, Xs, chunk: int = 4096):
     mean = np.empty(Xs.shape[0])
     var = np.empty(Xs.shape[0])
     for s in range(0, Xs.shape[0], chunk):
-        Ps = eigenfunctions_nd(Xs[s:s + chunk], f.eps, f.alpha, f.n, f.order)
+        Ps = eigenfunctions_nd(Xs[s:s + chunk], f.eps, f.alpha, f.n, f.order, kernel=f.kernel)
         mean[s:s + chunk] = Ps @ f.w
         Z = sla.lu_solve(f.lu, Ps.T)                   # A^-1 Phi_*^T
         var[s:s + chunk] = f.sigma ** 2 * np.einsum("im,mi->i", Ps, Z)
@@ -248,7 +325,7 @@ def predict_cov(f: Fit, Xs, chunk: int = 4096):
     form): Sigma_* = sigma^2 Phi_* A^-1 Phi_*^T, N_* x N_*.  Its diagonal is
     predict()'s variance."""
     Xs = np.atleast_2d(np.asarray(Xs, dtype=np.float64))
-    Ps = eigenfunctions_nd(Xs, f.eps, f.alpha, f.n, f.order)
+    Ps = eigenfunctions_nd(Xs, f.eps, f.alpha, f.n, f.order, kernel=f.kernel)
     Z = sla.lu_solve(f.lu, Ps.T)                        # A^-1 Phi_*^T
     return f.sigma ** 2 * (Ps @ Z)
 
@@ -274,11 +351,11 @@ def log_marginal_likelihood(f: Fit, y):
 # --------------------------------------------------------------------------
 # Alternative formulations (small N only), used to pin F1
 # --------------------------------------------------------------------------
-def log_marginal_likelihood_nxn(X, y, sigma, eps, alpha, n):
+def log_marginal_likelihood_nxn(X, y, sigma, eps, alpha, n, kernel: str = "se"):
     """log N(y; 0, K~ + sigma^2 I) with the N x N truncated kernel (7),
     evaluated by its definition (Cholesky of the N x N covariance)."""
     y = np.asarray(y, dtype=np.float64).reshape(-1)
-    S = truncated_kernel(X, X, eps, alpha, n) + sigma * sigma * np.eye(y.shape[0])
+    S = truncated_kernel(X, X, eps, alpha, n, kernel) + sigma * sigma * np.eye(y.shape[0])
     L = np.linalg.cholesky(S)
     a = sla.solve_triangular(L, y, lower=True)
     return -0.5 * float(a @ a) - float(np.sum(np.log(np.diag(L)))) - 0.5 * y.shape[0] * math.log(2.0 * math.pi)
@@ -304,12 +381,12 @@ def posterior_woodbury_W(X, y, Xs, sigma, eps, alpha, n):
     return mean, cov
 
 
-def posterior_truncated_nxn(X, y, Xs, sigma, eps, alpha, n):
+def posterior_truncated_nxn(X, y, Xs, sigma, eps, alpha, n, kernel: str = "se"):
     """F3: eqs. (8)-(9), the GP posterior with the truncated kernel (7) and
     the N x N system (K~ + sigma^2 I).  Returns (mean, full covariance)."""
-    K = truncated_kernel(X, X, eps, alpha, n)
-    Ks = truncated_kernel(Xs, X, eps, alpha, n)
-    Kss = truncated_kernel(Xs, Xs, eps, alpha, n)
+    K = truncated_kernel(X, X, eps, alpha, n, kernel)
+    Ks = truncated_kernel(Xs, X, eps, alpha, n, kernel)
+    Kss = truncated_kernel(Xs, Xs, eps, alpha, n, kernel)
     S = K + sigma * sigma * np.eye(K.shape[0])
     mean = Ks @ np.linalg.solve(S, np.asarray(y, dtype=np.float64))
     cov = Kss - Ks @ np.linalg.solve(S, Ks.T)
@@ -321,6 +398,22 @@ def posterior_exact_se(X, y, Xs, sigma, eps):
     K = se_ard_kernel(X, X, eps)
     Ks = se_ard_kernel(Xs, X, eps)
     Kss = se_ard_kernel(Xs, Xs, eps)
+    S = K + sigma * sigma * np.eye(K.shape[0])
+    mean = Ks @ np.linalg.solve(S, np.asarray(y, dtype=np.float64))
+    cov = Kss - Ks @ np.linalg.solve(S, Ks.T)
+    return mean, cov
+
+
+def posterior_exact(X, y, Xs, sigma, eps, alpha, kernel: str = "se"):
+    """Eqs. (3)-(4) with m = 0 and the closed-form kernel of the family: the
+    ARD SE kernel (17) or the product periodic kernel."""
+    if kernel == "se":
+        return posterior_exact_se(X, y, Xs, sigma, eps)
+    if kernel != "periodic":
+        raise ValueError(f"unknown kernel {kernel!r}")
+    K = periodic_ard_kernel(X, X, eps, alpha)
+    Ks = periodic_ard_kernel(Xs, X, eps, alpha)
+    Kss = periodic_ard_kernel(Xs, Xs, eps, alpha)
     S = K + sigma * sigma * np.eye(K.shape[0])
     mean = Ks @ np.linalg.solve(S, np.asarray(y, dtype=np.float64))
     cov = Kss - Ks @ np.linalg.solve(S, Ks.T)

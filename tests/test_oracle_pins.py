@@ -295,10 +295,10 @@ def test_pin_catches_wrong_multi_index_order(monkeypatch):
     another breaks the tensor factorisation."""
     real = o.eigenfunctions_nd
 
-    def swapped(X, eps, alpha, n, order=None):
+    def swapped(X, eps, alpha, n, order=None, kernel="se"):
         X = np.atleast_2d(X)
         idx = o.multi_indices(n, X.shape[1])[:, ::-1] if order is None else order
-        return real(X, eps, alpha, n, idx)
+        return real(X, eps, alpha, n, idx, kernel=kernel)
     _with(monkeypatch, "eigenfunctions_nd", swapped)
     with pytest.raises(AssertionError):
         test_tensor_factorisation()
@@ -365,3 +365,111 @@ def test_pin_catches_dropped_eigenvalue_logdet(monkeypatch):
     monkeypatch.setattr(o, "log_marginal_likelihood", broken)
     with pytest.raises(AssertionError):
         test_log_marginal_likelihood_equals_gaussian_density(2, 5, 0.05, [1.0, 1.3], [1.2, 0.9])
+
+
+# ---------------------------------------------------------------- periodic kernel (other Mercer kernels)
+def periodic_1d(x1, x2, eps, alpha):
+    """exp(-2 eps^2 sin^2(alpha (x - x') / 2)), written out."""
+    return np.exp(-2.0 * eps ** 2 * np.sin(alpha * (x1[:, None] - x2[None, :]) / 2.0) ** 2)
+
+
+@pytest.mark.parametrize("eps,alpha", [(0.5, 1.0), (1.0, 2.0), (2.0, 0.7)])
+def test_periodic_expansion_reproduces_kernel(eps, alpha):
+    """Jacobi-Anger: the expansion (1, sqrt2 cos, sqrt2 sin with e^-a I_k(a))
+    truncated at 61 columns is the periodic kernel to rounding."""
+    x = np.linspace(-4.0, 4.0, 41)
+    K = periodic_1d(x, x, eps, alpha)
+    lam = o.periodic_eigenvalues_1d(eps, 61)
+    Phi = o.periodic_eigenfunctions_1d(x, eps, alpha, 61)
+    assert np.max(np.abs((Phi * lam) @ Phi.T - K)) < 1e-14
+
+
+@pytest.mark.parametrize("eps", [0.3, 1.0, 3.0])
+def test_periodic_eigenvalues_power_series(eps):
+    """e^-a I_k(a) against its power series e^-a sum_m (a/2)^(2m+k) / (m! (m+k)!)
+    summed here in log space (not the library routine the oracle calls)."""
+    a = eps * eps
+    lam = o.periodic_eigenvalues_1d(eps, 21)
+    for c in range(21):
+        k = (c + 1) // 2
+        ser = sum(math.exp((2 * m + k) * math.log(a / 2.0) - math.lgamma(m + 1) - math.lgamma(m + k + 1) - a)
+                  for m in range(200))
+        assert abs(lam[c] - ser) <= 1e-14 * ser
+
+
+@pytest.mark.parametrize("eps", [0.7, 2.0])
+def test_periodic_eigenvalue_trace_is_one(eps):
+    """sum of all eigenvalues = k(x, x) = 1; cos and sin of a harmonic share theirs."""
+    lam = o.periodic_eigenvalues_1d(eps, 81)
+    assert abs(lam.sum() - 1.0) < 1e-14
+    assert np.array_equal(lam[1::2][:40], lam[2::2][:40])
+    assert np.all(np.diff(lam[::2]) < 0)
+
+
+def test_periodic_eigenfunctions_orthonormal():
+    """Mean of phi_i phi_j over one period (a uniform grid of 256 points
+    integrates trigonometric polynomials of degree < 256 exactly) = delta_ij."""
+    alpha = 1.7
+    x = np.arange(256) * (2.0 * math.pi / alpha) / 256 - 3.0
+    Phi = o.periodic_eigenfunctions_1d(x, 1.0, alpha, 31)
+    assert np.max(np.abs(Phi.T @ Phi / 256 - np.eye(31))) < 1e-13
+
+
+def test_periodic_closed_form_p2():
+    x1 = np.random.default_rng(5).uniform(-3, 3, (30, 2))
+    x2 = np.random.default_rng(6).uniform(-3, 3, (20, 2))
+    K = periodic_1d(x1[:, 0], x2[:, 0], 0.8, 1.1) * periodic_1d(x1[:, 1], x2[:, 1], 1.3, 2.0)
+    assert np.max(np.abs(o.periodic_ard_kernel(x1, x2, [0.8, 1.3], [1.1, 2.0]) - K)) < 1e-15
+    Kt = o.truncated_kernel(x1, x2, [0.8, 1.3], [1.1, 2.0], 41, "periodic")
+    assert np.max(np.abs(Kt - K)) < 1e-14
+
+
+@pytest.mark.parametrize("p,n", [(1, 7), (2, 5)])
+def test_periodic_weight_space_equals_nxn_truncated_posterior(p, n):
+    rng = np.random.default_rng(11 + p)
+    X = rng.uniform(-3, 3, (150, p))
+    y = np.sin(1.5 * X).sum(axis=1) + 0.05 * rng.standard_normal(150)
+    Xs = rng.uniform(-3, 3, (40, p))
+    f = o.fit(X, y, 0.1, 0.9, 1.5, n, kernel="periodic")
+    mean, var = o.predict(f, Xs)
+    m3, c3 = o.posterior_truncated_nxn(X, y, Xs, 0.1, 0.9, 1.5, n, "periodic")
+    assert rel(mean, m3) < 1e-10
+    assert rel(var, np.diag(c3)) < 1e-9
+    assert rel(o.predict_cov(f, Xs), c3) < 1e-9
+    lml = o.log_marginal_likelihood(f, y)
+    assert abs(lml - o.log_marginal_likelihood_nxn(X, y, 0.1, 0.9, 1.5, n, "periodic")) < 1e-9 * abs(lml)
+
+
+def test_periodic_weight_space_tends_to_exact_posterior():
+    """With 41 columns the truncated-kernel posterior is the exact periodic
+    GP posterior (eqs. 3-4 with the closed-form kernel)."""
+    rng = np.random.default_rng(3)
+    X = rng.uniform(-3, 3, (120, 1))
+    y = np.cos(2.0 * X[:, 0]) + 0.05 * rng.standard_normal(120)
+    Xs = rng.uniform(-3, 3, (30, 1))
+    f = o.fit(X, y, 0.1, 1.2, 2.0, 41, kernel="periodic")
+    mean, var = o.predict(f, Xs)
+    me, ce = o.posterior_exact(X, y, Xs, 0.1, 1.2, 2.0, "periodic")
+    assert rel(mean, me) < 1e-9
+    assert np.max(np.abs(var - np.diag(ce))) < 1e-9
+
+
+def test_pin_catches_periodic_without_sqrt2(monkeypatch):
+    """Unnormalised cos/sin features (or e^-a dropped from I_k) break the
+    closed-form pin and orthonormality."""
+    real = o.periodic_eigenfunctions_1d
+    _with(monkeypatch, "periodic_eigenfunctions_1d",
+          lambda x, eps, alpha, n: real(x, eps, alpha, n) / np.where(np.arange(n) > 0, math.sqrt(2.0), 1.0))
+    with pytest.raises(AssertionError):
+        test_periodic_expansion_reproduces_kernel(1.0, 2.0)
+    with pytest.raises(AssertionError):
+        test_periodic_eigenfunctions_orthonormal()
+
+
+def test_pin_catches_unscaled_bessel(monkeypatch):
+    _with(monkeypatch, "periodic_eigenvalues_1d",
+          lambda eps, n: sps.iv((np.arange(n) + 1) // 2, eps * eps))
+    with pytest.raises(AssertionError):
+        test_periodic_expansion_reproduces_kernel(1.0, 2.0)
+    with pytest.raises(AssertionError):
+        test_periodic_eigenvalue_trace_is_one(0.7)
