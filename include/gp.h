@@ -68,18 +68,33 @@ typedef enum {
                             same tolerances hold for both                      */
 } gp_precision;
 
+typedef enum {
+  GP_KERNEL_SE = 0,       /* squared exponential (Sec. 2.3, eqs. 13-20)          */
+  GP_KERNEL_PERIODIC = 1  /* periodic (exp-sine-squared), per dimension
+                             k = exp(-2 eps^2 sin^2(alpha (x - x') / 2)): one of
+                             the other Mercer kernels Sec. 2.3 mentions.  Its
+                             expansion on one period (Jacobi-Anger): features
+                             1, sqrt2 cos(k alpha x), sqrt2 sin(k alpha x),
+                             eigenvalues e^-a I_0(a), then e^-a I_k(a) for
+                             both of harmonic k, a = eps^2                     */
+} gp_kernel;
+
 /* Limits enforced by validation. */
 #define GP_MAX_P 8
 #define GP_MAX_N 64
 #define GP_MAX_M 16384
+#define GP_MAX_PERIODIC_EPS 16.0   /* periodic kernel: eps_j <= this            */
 
 /* Problem parameters (Sec. 2.1 problem statement; eqs. 13-20).
  *  p      input dimension, 1..GP_MAX_P
  *  n      eigenvalues per dimension, 1..GP_MAX_N; M = n^p <= GP_MAX_M
  *  sigma  noise standard deviation, > 0 (Sigma_n = sigma^2 I, Sec. 2.2)
- *  eps    host [p]: ARD length scales eps_j > 0 (eq. 17)
- *  alpha  host [p]: global scale factors rho_j > 0 (eqs. 14-16, 19-20)
- *  precision  gp_precision                                                   */
+ *  eps    host [p]: ARD length scales eps_j > 0 (eq. 17); periodic kernel:
+ *         inverse length scales, 0 < eps_j <= GP_MAX_PERIODIC_EPS
+ *  alpha  host [p]: global scale factors rho_j > 0 (eqs. 14-16, 19-20);
+ *         periodic kernel: angular frequencies (period 2 pi / alpha_j) > 0
+ *  precision  gp_precision
+ *  kernel     gp_kernel (0, the SE kernel, when the field is zeroed)       */
 typedef struct {
   int32_t p;
   int32_t n;
@@ -87,6 +102,7 @@ typedef struct {
   const double *eps;
   const double *alpha;
   int32_t precision;
+  int32_t kernel;
 } gp_params;
 
 typedef struct gp_ctx gp_ctx;      /* one GPU: streams, workspace, scheduler   */

@@ -18,6 +18,7 @@ GP_EINVAL, GP_ENOMEM, GP_ENOTSPD, GP_EDEVICE, GP_ENOTFOUND, GP_ECANCELED = -1, -
 STATUS_NAMES = {0: "GP_OK", 1: "GP_PENDING", -1: "GP_EINVAL", -2: "GP_ENOMEM", -3: "GP_ENOTSPD",
                 -4: "GP_EDEVICE", -5: "GP_ENOTFOUND", -6: "GP_ECANCELED"}
 PREC_FP64, PREC_MIXED, PREC_MIXED_F16 = 0, 1, 2
+KERNEL_SE, KERNEL_PERIODIC = 0, 1
 MODEL_W, MODEL_LAMBDA, MODEL_A, MODEL_B, MODEL_L, MODEL_LINV = range(6)
 REQ_FIT, REQ_PREDICT, REQ_FIT_PREDICT = 0, 1, 2
 MAX_P, MAX_N, MAX_M = 8, 64, 16384
@@ -33,7 +34,7 @@ PHASES = ["gram", "gram_reduce", "phiT", "chol", "trtri", "solve", "split", "pre
 class GpParams(C.Structure):
     _fields_ = [("p", C.c_int32), ("n", C.c_int32), ("sigma", C.c_double),
                 ("eps", C.POINTER(C.c_double)), ("alpha", C.POINTER(C.c_double)),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("kernel", C.c_int32)]
 
 
 class GpRequest(C.Structure):
@@ -126,12 +127,12 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
-def make_params(p, n, sigma, eps, alpha, precision=PREC_FP64):
+def make_params(p, n, sigma, eps, alpha, precision=PREC_FP64, kernel=KERNEL_SE):
     import numpy as np
     e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (p,)))
     a = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha, dtype=np.float64), (p,)))
     prm = GpParams(p, n, float(sigma), e.ctypes.data_as(C.POINTER(C.c_double)),
-                   a.ctypes.data_as(C.POINTER(C.c_double)), precision)
+                   a.ctypes.data_as(C.POINTER(C.c_double)), precision, kernel)
     prm._keep = (e, a)
     return prm
 
@@ -223,8 +224,8 @@ class Context:
             out[name] = (ms.value, cnt.value)
         return out
 
-    def fit(self, x, y, *, p, n, sigma, eps, alpha, precision=PREC_FP64, stream=None) -> Model:
-        prm = make_params(p, n, sigma, eps, alpha, precision)
+    def fit(self, x, y, *, p, n, sigma, eps, alpha, precision=PREC_FP64, kernel=KERNEL_SE, stream=None) -> Model:
+        prm = make_params(p, n, sigma, eps, alpha, precision, kernel)
         out = C.c_void_p()
         N = y.shape[0] if y is not None else 0
         _check(load().gp_fit(self.handle, C.byref(prm), _ptr(x), _ptr(y), N, _stream(stream), C.byref(out)))
@@ -252,11 +253,11 @@ class Context:
                                      _stream(stream)))
         return cov
 
-    def learn(self, x, y, *, p, n, sigma, eps, alpha, precision=PREC_FP64, max_evals=150, per_dim=False,
-              learn_alpha=True, learn_sigma=True, tol=1e-6, stream=None):
+    def learn(self, x, y, *, p, n, sigma, eps, alpha, precision=PREC_FP64, kernel=KERNEL_SE, max_evals=150,
+              per_dim=False, learn_alpha=True, learn_sigma=True, tol=1e-6, stream=None):
         """gp_learn: returns (eps[p], alpha[p], sigma, lml, evals) of the best point."""
         import numpy as np
-        prm = make_params(p, n, sigma, eps, alpha, precision)
+        prm = make_params(p, n, sigma, eps, alpha, precision, kernel)
         opts = GpLearnOpts(max_evals, int(per_dim), int(learn_alpha), int(learn_sigma), tol)
         e_out = np.zeros(p)
         a_out = np.zeros(p)
@@ -272,9 +273,10 @@ class Context:
         _check(load().gp_autotune(self.handle, p, n, N, C.byref(c)))
         return c.value
 
-    def fit_batch(self, problems, precision=PREC_MIXED, stream=None):
+    def fit_batch(self, problems, precision=PREC_MIXED, kernel=KERNEL_SE, stream=None):
         """problems: list of (x, y, p, n, sigma, eps, alpha) with device x, y;
-        precision: one gp_precision for all, or one per problem."""
+        precision: one gp_precision for all, or one per problem; kernel: one
+        gp_kernel for all."""
         k = len(problems)
         precs = [precision] * k if isinstance(precision, int) else list(precision)
         if len(precs) != k:
@@ -282,7 +284,7 @@ class Context:
         prms = (GpParams * k)()
         keep = []
         for i, (x, y, p, n, sigma, eps, alpha) in enumerate(problems):
-            prm = make_params(p, n, sigma, eps, alpha, precs[i])
+            prm = make_params(p, n, sigma, eps, alpha, precs[i], kernel)
             keep.append(prm._keep)
             prms[i] = prm
         xs = (C.c_void_p * k)(*[_ptr(pr[0]).value for pr in problems])

@@ -50,6 +50,12 @@ gp_status validate_params(const gp_params* prm, int64_t* M_out) {
   }
   if (prm->precision != GP_PREC_FP64 && !prec_mixed(prm->precision))
     return fail(GP_EINVAL, "unknown precision %d", prm->precision);
+  if (prm->kernel != GP_KERNEL_SE && prm->kernel != GP_KERNEL_PERIODIC)
+    return fail(GP_EINVAL, "unknown kernel %d", prm->kernel);
+  if (prm->kernel == GP_KERNEL_PERIODIC)
+    for (int j = 0; j < prm->p; ++j)
+      if (prm->eps[j] > GP_MAX_PERIODIC_EPS)
+        return fail(GP_EINVAL, "periodic kernel: eps[%d]=%g above %g", j, prm->eps[j], GP_MAX_PERIODIC_EPS);
   *M_out = M;
   return GP_OK;
 }
@@ -173,6 +179,7 @@ gp_status model_alloc(gp_ctx* ctx, const gp_params* prm, int64_t M, bool lean, h
   m->n = prm->n;
   m->M = M;
   m->precision = prm->precision;
+  m->kernel = prm->kernel;
   m->sigma = prm->sigma;
   for (int j = 0; j < prm->p; ++j) {
     m->eps[j] = prm->eps[j];
@@ -225,6 +232,7 @@ void enqueue_fit_head(gp_model* m, const double* x, const double* y, int64_t N, 
   memset(&a, 0, sizeof(a));
   a.p = p;
   a.n = n;
+  a.kind = m->kernel;
   a.sigma = m->sigma;
   for (int j = 0; j < p; ++j) {
     a.eps[j] = m->eps[j];

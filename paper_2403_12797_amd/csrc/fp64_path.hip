@@ -32,7 +32,7 @@ __device__ __forceinline__ void fill_tab_cf64(const double* __restrict__ x, int6
     double* o = out + i * ld + j * n;
     if (row < N) {
       const double* dc = tab + kTabDim + j * kDimStride;
-      phi_1d<double, double>(x[row * p + j], dc[0], dc[1], dc[2], rc1, rc2, n, o, 1);
+      phi_1d<double, double>(x[row * p + j], dc, rc1, rc2, n, o, 1);
     } else {
       for (int k = 0; k < n; ++k) o[k] = 0.0;
     }
@@ -929,7 +929,7 @@ __global__ void __launch_bounds__(256) predict_var_f64_kernel(const double* __re
       double* o = T + (j * n) * kPvTn + i;
       if (i0 + i < Ns) {
         const double* dc = tab + kTabDim + j * kDimStride;
-        phi_1d<double, double>(xs[(i0 + i) * p + j], dc[0], dc[1], dc[2], rc1, rc2, n, o, kPvTn);
+        phi_1d<double, double>(xs[(i0 + i) * p + j], dc, rc1, rc2, n, o, kPvTn);
       } else {
         for (int k = 0; k < n; ++k) o[k * kPvTn] = 0.0;
       }

@@ -7,6 +7,7 @@ namespace mgp {
 
 struct EigArgs {
   int p, n;
+  int kind;   // gp_kernel
   double sigma;
   double eps[GP_MAX_P];
   double alpha[GP_MAX_P];

@@ -52,20 +52,35 @@ __global__ void __launch_bounds__(256) phi1d_table_kernel(const double* __restri
     const int64_t st = u / ((int64_t)kGmKC * p);
     const int64_t row = st * kGmKC + i;
     float* o = out + (st * p * n + (int64_t)j * n) * kGmKC + i;
-    // phi_{k+1}(x) = sqrt(beta) exp(-delta^2 x^2) h_k(alpha beta x), h_k the
-    // normalised Hermite recurrence (eq. 15); zero past the last sample
+    // SE: phi_{k+1}(x) = sqrt(beta) exp(-delta^2 x^2) h_k(alpha beta x), h_k
+    // the normalised Hermite recurrence (eq. 15); periodic: 1, then sqrt2 cos
+    // and sqrt2 sin of each harmonic of alpha x (as phi_1d); zero past the
+    // last sample
     const double* dc = tab + kTabDim + j * kDimStride;
     const double* rc1 = tab + kTabRc1;
     const double* rc2 = tab + kTabRc2;
     const bool live = row < N;
+    const bool per = dc[3] != 0.0;
     const double xv = live ? x[row * p + j] : 0.0;
     const double t = dc[0] * xv;
-    const double e = live ? dc[2] * exp(-dc[1] * xv * xv) : 0.0;
+    const double e = live ? (per ? 1.0 : dc[2] * exp(-dc[1] * xv * xv)) : 0.0;
     double h0 = 1.0, h1 = 1.4142135623730951 * t;
+    double s1 = 0.0, c1 = 1.0;
+    if (per) sincos(t, &s1, &c1);
+    double hc = c1, hs = s1;   // periodic: cos and sin of the current harmonic
     for (int k = 0; k < n; ++k) {
       double hk;
       if (k == 0) {
         hk = 1.0;
+      } else if (per) {
+        if (k & 1) {
+          hk = 1.4142135623730951 * hc;
+        } else {
+          hk = 1.4142135623730951 * hs;
+          const double cn = hc * c1 - hs * s1;
+          hs = hs * c1 + hc * s1;
+          hc = cn;
+        }
       } else if (k == 1) {
         hk = h1;
       } else {
@@ -877,7 +892,7 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     float* o = Tf + (j * n) * TN + i;
     if (i0 + i < Ns) {
       const double* dc = tab + kTabDim + j * kDimStride;
-      phi_1d<double, float>(xs[(i0 + i) * P + j], dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, TN);
+      phi_1d<double, float>(xs[(i0 + i) * P + j], dc, tab + kTabRc1, tab + kTabRc2, n, o, TN);
     } else {
       for (int k = 0; k < n; ++k) o[k * TN] = 0.0f;
     }

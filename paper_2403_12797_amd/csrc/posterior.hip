@@ -21,7 +21,7 @@ __global__ void __launch_bounds__(256) phi_dense_kernel(const double* __restrict
     double* o = T + i * rows + j * n;
     if (i0 + i < Ns) {
       const double* dc = tab + kTabDim + j * kDimStride;
-      phi_1d<double, double>(xs[(i0 + i) * p + j], dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, 1);
+      phi_1d<double, double>(xs[(i0 + i) * p + j], dc, tab + kTabRc1, tab + kTabRc2, n, o, 1);
     } else {
       for (int k = 0; k < n; ++k) o[k] = 0.0;
     }

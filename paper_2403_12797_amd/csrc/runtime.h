@@ -22,6 +22,7 @@ struct gp_model {
   int p = 0, n = 0;
   int64_t M = 0;
   int precision = 0;
+  int kernel = 0;   // gp_kernel
   double sigma = 0.0;
   double eps[GP_MAX_P] = {};
   double alpha[GP_MAX_P] = {};

@@ -4,11 +4,41 @@
 namespace mgp {
 
 // ---------------------------------------------------------------- a1
+// e^-a I_k(a) (the periodic kernel's eigenvalues, a = eps^2 <= 256) by its
+// power series sum_m e^-a (a/2)^(2m+k) / (m! (m+k)!): positive terms, the
+// first in logarithms, the rest by their ratio (a/2)^2 / ((m+1)(m+k+1)),
+// summed until past the largest term and below 1e-18 of the sum.
+__device__ double bessel_i_scaled(int k, double a) {
+  if (a == 0.0) return k == 0 ? 1.0 : 0.0;
+  const double h = 0.5 * a, h2 = h * h;
+  double term = exp(k * log(h) - lgamma(k + 1.0) - a), sum = 0.0;
+  for (int m = 0; m < 4096; ++m) {
+    sum += term;
+    if (m > h && term < 1e-18 * sum) break;
+    term *= h2 / ((m + 1.0) * (m + k + 1.0));
+  }
+  return sum;
+}
+
 // Per-dimension scalars of eq. 14 (delta^2 = alpha^2/2 (beta^2-1)), the
-// eigenvalues of eq. 16 and the normalised Hermite recurrence coefficients.
+// eigenvalues of eq. 16 and the normalised Hermite recurrence coefficients
+// (SE); for the periodic kernel the angular frequencies and the Bessel
+// eigenvalues, one thread per (dimension, column).
 __global__ void eig_dim_kernel(EigArgs a, double* __restrict__ tab) {
   const int t = threadIdx.x;
-  if (t < a.p) {
+  if (a.kind == GP_KERNEL_PERIODIC) {
+    const int j = t / GP_MAX_N, k = t % GP_MAX_N;
+    if (j < a.p && k < a.n) {
+      if (k == 0) {
+        double* dc = tab + kTabDim + j * kDimStride;
+        dc[0] = a.alpha[j];
+        dc[1] = 0.0;
+        dc[2] = 1.0;
+        dc[3] = 1.0;
+      }
+      tab[kTabLam1 + j * GP_MAX_N + k] = bessel_i_scaled((k + 1) / 2, a.eps[j] * a.eps[j]);
+    }
+  } else if (t < a.p) {
     const double eps = a.eps[t], al = a.alpha[t];
     const double r = 2.0 * eps / al;
     const double beta = sqrt(sqrt(1.0 + r * r));
@@ -48,7 +78,7 @@ __global__ void eig_lambda_kernel(int p, int n, int M, double sigma2, const doub
 }
 
 void launch_eig_tables(const EigArgs& a, double* tab, double* lam, double* reg, int M, hipStream_t s) {
-  hipLaunchKernelGGL(eig_dim_kernel, dim3(1), dim3(64), 0, s, a, tab);
+  hipLaunchKernelGGL(eig_dim_kernel, dim3(1), dim3(GP_MAX_P * GP_MAX_N), 0, s, a, tab);
   hipLaunchKernelGGL(eig_lambda_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, a.p, a.n, M,
                      a.sigma * a.sigma, tab, lam, reg);
 }
@@ -69,7 +99,7 @@ __device__ __forceinline__ void fill_tab_sf(const double* __restrict__ x, int64_
     T* o = out + (j * n) * ld + i;
     if (row < N) {
       const double* dc = tab + kTabDim + j * kDimStride;
-      phi_1d<double, T>(x[row * p + j], dc[0], dc[1], dc[2], rc1, rc2, n, o, ld);
+      phi_1d<double, T>(x[row * p + j], dc, rc1, rc2, n, o, ld);
     } else {
       for (int k = 0; k < n; ++k) o[k * ld] = (T)0;
     }
@@ -88,7 +118,7 @@ __device__ __forceinline__ void fill_tab_cf(const double* __restrict__ x, int64_
     double* o = out + i * ld + j * n;
     if (row < N) {
       const double* dc = tab + kTabDim + j * kDimStride;
-      phi_1d<double, double>(x[row * p + j], dc[0], dc[1], dc[2], rc1, rc2, n, o, 1);
+      phi_1d<double, double>(x[row * p + j], dc, rc1, rc2, n, o, 1);
     } else {
       for (int k = 0; k < n; ++k) o[k] = 0.0;
     }
@@ -322,7 +352,7 @@ __global__ void __launch_bounds__(256) phiT_gemm_kernel(const double* __restrict
       double* o = T + (xj * n) * kTvLd + xi;
       if (row < c1) {
         const double* dc = tab + kTabDim + xj * kDimStride;
-        phi_1d<double, double>(xc, dc[0], dc[1], dc[2], tab + kTabRc1, tab + kTabRc2, n, o, kTvLd);
+        phi_1d<double, double>(xc, dc, tab + kTabRc1, tab + kTabRc2, n, o, kTvLd);
       } else {
         for (int k = 0; k < n; ++k) o[k * kTvLd] = 0.0;
       }

@@ -131,6 +131,20 @@ def random_problem(seed: int, p: int, n: int, N: int, Ns: int, *, dist: str = "u
     return Problem(f"rand{seed}_p{p}_n{n}_N{N}", p, n, sigma, eps, alpha, x, y, xs)
 
 
+def periodic_problem(seed: int, p: int, n: int, N: int, Ns: int, *, sigma: float = 0.1, eps=None,
+                     alpha=None) -> Problem:
+    """A random problem for the periodic kernel: x, x* ~ U[-3, 3]^p (a few
+    periods at the drawn angular frequencies alpha ~ U[0.8, 2]),
+    y = sum_d sin(alpha_d x_d + d) + N(0, sigma^2), eps ~ U[0.5, 1.5]."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_BASE, 77, seed])))
+    x = g.uniform(-3.0, 3.0, size=(N, p))
+    xs = g.uniform(-3.0, 3.0, size=(Ns, p))
+    eps = g.uniform(0.5, 1.5, size=p) if eps is None else np.broadcast_to(np.asarray(eps, float), (p,)).copy()
+    alpha = g.uniform(0.8, 2.0, size=p) if alpha is None else np.broadcast_to(np.asarray(alpha, float), (p,)).copy()
+    y = np.sin(alpha * x + np.arange(p)).sum(axis=1) + g.normal(0.0, sigma, size=N)
+    return Problem(f"per{seed}_p{p}_n{n}_N{N}", p, n, sigma, eps, alpha, x, y, xs, meta={"kernel": "periodic"})
+
+
 def batched_problems(count: int = 256, *, N_max: int = 200_000) -> list[Problem]:
     """Many independent problems of uneven shape: p ~ U{1,2,3}, one n ~ U{4..12}
     for all dims, N log-uniform in [1e3, N_max], N_* = N, x ~ N(0, I_p),
