@@ -274,29 +274,32 @@ __global__ void __launch_bounds__(kPfThreads) potrf_diag_kernel(double* __restri
   }
 }
 
-// The same factor and inverse with W waves (4 by default, 2 behind a knob).
+// The same factor and inverse with W waves (launched with 4).
 // Lane i of wave H holds row i of the block, columns C H .. C H + C - 1
-// (C = 64 / W), in registers; wave H owns those columns and factors them
-// while the waves right of it apply their updates to their own columns.
-// The owner works in blocks of 8 steps whose body is unrolled, shifting its
-// registers down by 8 after each block, so the pivot column of step 8b + k
-// is always register k.  Step K keeps the pivot chain in registers: column
-// K of L, l (lane i: B[i][K] r with r = 1/sqrt(B[K][K]), L[K][K] = d r, zero
-// above), was formed at the end of the previous step; it is stored in LDS
-// (transposed: Lt[K][i]), column K+1 gets its update from l and l_{K+1}
-// (read from lane K+1), and its pivot is read from lane K+1 and turned into
-// the next l.  Meanwhile every register takes the rank-1 update of the
-// previous step, l_j read back from LDS (the wave's own writes, in order,
-// stored a step earlier), so the LDS round trip stays off the pivot chain;
-// registers of columns already factored, or past the wave's columns,
-// collect values that are never read.  The waves right of the owner apply a
-// block's 8 updates after the block's barrier.  r comes from the hardware
-// estimate and two Newton steps.  A failing pivot is recorded and replaced
-// by 1 so the loop runs to the end.  Then X = L^-1 by forward substitution
-// in the same pattern, lane c owning column c and wave H rows C H ..
-// C H + C - 1: row r is final in register 0 of its owner, scaled by
-// 1/L[r][r], stored to LDS and subtracted from the later rows.  L and X
-// leave through LDS.  Rows and columns past the matrix are the identity.
+// (C = 64 / W), in registers, and the same rows of the identity that
+// become X = L^-1 (X[r][i] in lane i, rows C H .. C H + C - 1); wave H
+// owns those columns and factors them while the waves right of it apply
+// their updates.  The owner works in blocks of 8 steps whose body is
+// unrolled, shifting its registers down by 8 after each block, so the pivot
+// column of step 8b + k is always register k.  Step K keeps the pivot chain
+// in registers: column K of L, l (lane i: B[i][K] r with r = 1/sqrt(B[K][K]),
+// L[K][K] = d r, zero above), was formed at the end of the previous step; it
+// is stored in LDS (transposed: Lt[K][i]), column K+1 gets its update from l
+// and l_{K+1} (read from lane K+1), and its pivot is read from lane K+1 and
+// turned into the next l.  Row K of X is the forward-substitution row
+// (e_K - sum_{j<K} L[K][j] X_j) / L[K][K]: its last term, from row K-1, is
+// taken here, the others were applied before.  Meanwhile every register
+// takes the rank-1 update of the previous step, l_j read back from LDS (the
+// wave's own writes, in order, stored a step earlier), so the LDS round trip
+// stays off the pivot chain; the same multipliers L[j][K-1] update the rows
+// of X with row K-1 of X.  Registers of columns already factored, or past
+// the wave's columns, collect values that are never read.  The waves right
+// of the owner apply a block's 8 updates of both after the block's barrier.
+// Column K of L and row K of X leave for global memory as soon as they are
+// formed.  r comes from the hardware estimate and two Newton steps.  A
+// failing pivot is recorded and replaced by 1 so the loop runs to the end
+// (what was written is then meaningless; info says so).  Rows and columns
+// past the matrix are the identity.
 constexpr int kPdNone = kNb + 1;
 constexpr int kD2Blk = 8;    // steps per unrolled block
 // Lt pitch for W waves of 64 / W columns: the owner's shifted registers reach
@@ -339,25 +342,27 @@ __global__ void __launch_bounds__(64 * W) potrf_diag2_kernel(double* __restrict_
   static_assert(C % kD2Blk == 0 && C % 4 == 0, "wave columns");
   __shared__ double Lt[kNb * Ld];   // Lt[j][i] = L[i][j]
   __shared__ double Xs[kNb * kNb];     // X[r][c]
-  __shared__ double rdiag[kNb];        // 1 / L[k][k]
   __shared__ int sbad;
   if (*info) return;
   const int t = threadIdx.x, i = t & 63;
   const int H = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nb = min(kNb, M - k0);
+  double* D = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
   for (int e = t; e < kNb * (Ld - kNb); e += 64 * W) Lt[(e / (Ld - kNb)) * Ld + kNb + e % (Ld - kNb)] = 0.0;
   if (t == 0) sbad = kPdNone;
-  double a[C];
+  double a[C], x[C];
   // row j of the (symmetric) block, read coalesced: lane i takes B[j][i] = B[i][j]
 #pragma unroll
   for (int jl = 0; jl < C; ++jl) {
     const int j = C * H + jl;
     a[jl] = (i < nb && j < nb) ? A[(int64_t)(k0 + j) * M + k0 + i] : (i == j ? 1.0 : 0.0);
+    x[jl] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
   int bad = 0;
   double l = 0.0, rk = 1.0;   // the owner's next column of L and its 1/L[K][K]
   double lp = 0.0;            // the owner's previous column, whose rank-1 update is pending
+  double xp = 0.0;            // the owner's previous row of X, whose update is pending
 #pragma unroll 1
   for (int b = 0; b < kNb / kD2Blk; ++b) {
     const int K0 = kD2Blk * b;
@@ -366,13 +371,13 @@ __global__ void __launch_bounds__(64 * W) potrf_diag2_kernel(double* __restrict_
       if (first_blk) {
         d2_pivot(a[0], K0, i, true, l, rk, bad);
         lp = 0.0;
+        xp = 0.0;
       }
       const bool last_blk = b % BPW == BPW - 1;
 #pragma unroll
       for (int kl = 0; kl < kD2Blk; ++kl) {
         const int K = K0 + kl;
         Lt[K * Ld + i] = l;
-        rdiag[K] = rk;
         // The rank-1 update of step K is applied one step late, from the row
         // stored a step earlier (its LDS round trip off the pivot chain); the
         // next column takes the pending update and this step's from lanes
@@ -390,7 +395,7 @@ __global__ void __launch_bounds__(64 * W) potrf_diag2_kernel(double* __restrict_
           for (int jl = 0; jl < C; ++jl) lv[jl] = 0.0;
         }
         // the pivot chain of the next column in segments, each followed by a
-        // quarter of the pending rank-1 update, so that its latency hides
+        // quarter of the pending rank-1 updates, so that its latency hides
         // under them
         const int k1 = min(K + 1, kNb - 1);
         const double c = fma(-l, readlane_f64(l, k1), fma(-lp, readlane_f64(lp, k1), a[kl + 1]));
@@ -401,29 +406,51 @@ __global__ void __launch_bounds__(64 * W) potrf_diag2_kernel(double* __restrict_
         double r = __builtin_amdgcn_rsq(d);
         const double hd = -0.5 * d;
         __builtin_amdgcn_sched_barrier(0);
+        // row K of X (its update from row K - 1 pending until now), kept for
+        // the later waves and written out with column K of L
+        const double xk = fma(-readlane_f64(lp, K), xp, x[kl]) * rk;
+        Xs[K * kNb + i] = xk;
+        D[K * kNb + i] = (K < nb && i < nb && i <= K) ? xk : 0.0;
+        if (K < nb && i < nb) A[(int64_t)(k0 + i) * M + k0 + K] = l;
 #pragma unroll
-        for (int jl = 0; jl < C / 4; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
+        for (int jl = 0; jl < C / 4; ++jl) {
+          a[jl] = fma(-lp, lv[jl], a[jl]);
+          x[jl] = fma(-xp, lv[jl], x[jl]);
+        }
         __builtin_amdgcn_sched_barrier(0);
         r = r * fma(hd * r, r, 1.5);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int jl = C / 4; jl < C / 2; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
+        for (int jl = C / 4; jl < C / 2; ++jl) {
+          a[jl] = fma(-lp, lv[jl], a[jl]);
+          x[jl] = fma(-xp, lv[jl], x[jl]);
+        }
         __builtin_amdgcn_sched_barrier(0);
         r = r * fma(hd * r, r, 1.5);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int jl = C / 2; jl < 3 * C / 4; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
+        for (int jl = C / 2; jl < 3 * C / 4; ++jl) {
+          a[jl] = fma(-lp, lv[jl], a[jl]);
+          x[jl] = fma(-xp, lv[jl], x[jl]);
+        }
         __builtin_amdgcn_sched_barrier(0);
         const double ln = i > K + 1 ? c * r : (i == K + 1 ? d * r : 0.0);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int jl = 3 * C / 4; jl < C; ++jl) a[jl] = fma(-lp, lv[jl], a[jl]);
+        for (int jl = 3 * C / 4; jl < C; ++jl) {
+          a[jl] = fma(-lp, lv[jl], a[jl]);
+          x[jl] = fma(-xp, lv[jl], x[jl]);
+        }
         lp = l;
         l = ln;
         rk = r;
+        xp = xk;
       }
 #pragma unroll
-      for (int j = 0; j < C - kD2Blk; ++j) a[j] = a[j + kD2Blk];
+      for (int j = 0; j < C - kD2Blk; ++j) {
+        a[j] = a[j + kD2Blk];
+        x[j] = x[j + kD2Blk];
+      }
     }
     __syncthreads();
     if (b / BPW < H) {
@@ -431,70 +458,20 @@ __global__ void __launch_bounds__(64 * W) potrf_diag2_kernel(double* __restrict_
       for (int kl = 0; kl < kD2Blk; ++kl) {
         const int K = K0 + kl;
         const double li = Lt[K * Ld + i];
+        const double xk = Xs[K * kNb + i];
         const double* lr = Lt + K * Ld + C * H;
 #pragma unroll
-        for (int jl = 0; jl < C; ++jl) a[jl] = fma(-li, lr[jl], a[jl]);
+        for (int jl = 0; jl < C; ++jl) {
+          const double m = lr[jl];
+          a[jl] = fma(-li, m, a[jl]);
+          x[jl] = fma(-xk, m, x[jl]);
+        }
       }
     }
   }
   if (bad && i == 0) atomicMin(&sbad, bad);
   __syncthreads();
-  if (sbad != kPdNone) {
-    if (t == 0) *info = k0 + sbad;
-    return;
-  }
-  double x[C];   // rows C H + q of X (shifted like a), column i
-#pragma unroll
-  for (int q = 0; q < C; ++q) x[q] = C * H + q == i ? 1.0 : 0.0;
-#pragma unroll 1
-  for (int b = 0; b < kNb / kD2Blk; ++b) {
-    const int R0 = kD2Blk * b;
-    if (b / BPW == H) {
-      // (L and its diagonal are final: the block's 1/L[r][r] and each next
-      // row are read ahead of their step)
-      double rdv[kD2Blk], lc[C];
-#pragma unroll
-      for (int rl = 0; rl < kD2Blk; ++rl) rdv[rl] = rdiag[R0 + rl];
-#pragma unroll
-      for (int q = 0; q < C; ++q) lc[q] = Lt[R0 * Ld + R0 + q];
-#pragma unroll
-      for (int rl = 0; rl < kD2Blk; ++rl) {
-        const int r = R0 + rl;
-        double ln[C];
-        if (rl + 1 < kD2Blk) {
-#pragma unroll
-          for (int q = 0; q < C; ++q) ln[q] = Lt[(r + 1) * Ld + R0 + q];   // L[R0 + q][r + 1]
-        }
-        const double xr = x[rl] * rdv[rl];
-        Xs[r * kNb + i] = xr;
-#pragma unroll
-        for (int q = 0; q < C; ++q) x[q] = fma(-lc[q], xr, x[q]);   // L[R0 + q][r]
-        if (rl + 1 < kD2Blk) {
-#pragma unroll
-          for (int q = 0; q < C; ++q) lc[q] = ln[q];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < C - kD2Blk; ++q) x[q] = x[q + kD2Blk];
-    }
-    __syncthreads();
-    if (b / BPW < H) {
-#pragma unroll
-      for (int rl = 0; rl < kD2Blk; ++rl) {
-        const int r = R0 + rl;
-        const double xr = Xs[r * kNb + i];
-        const double* lr = Lt + r * Ld + C * H;   // L[C H + q][r]
-#pragma unroll
-        for (int q = 0; q < C; ++q) x[q] = fma(-lr[q], xr, x[q]);
-      }
-    }
-  }
-  // L (zeros above the diagonal) and X, each wave every other row, lane i = column
-  double* D = Dinv + (int64_t)(k0 / kNb) * kNb * kNb;
-  for (int r = H; r < kNb; r += W) {
-    if (r < nb && i < nb) A[(int64_t)(k0 + r) * M + k0 + i] = Lt[i * Ld + r];
-    D[r * kNb + i] = (r < nb && i < nb && i <= r) ? Xs[r * kNb + i] : 0.0;
-  }
+  if (sbad != kPdNone && t == 0) *info = k0 + sbad;
 }
 
 // One 64x64 output tile of C = sum_k A[m][k] B[k][n] with A, B row-major in
@@ -669,17 +646,10 @@ static int64_t update_tiles(int cb, int ce, int T) {
   return n;
 }
 
-// The two-wave-pattern diagonal factor on MGP_CHOL_W waves (2 or 4; a
-// tuning knob, default 4).
-static int chol_waves() {
-  const char* v = getenv("MGP_CHOL_W");
-  return v && atoi(v) == 2 ? 2 : 4;
-}
+// The register-resident diagonal factor on four waves of 16 columns (two
+// waves of 32 would need a, x and the broadcast row in 192 registers).
 static void launch_diag2(double* A, int M, int k0, double* Dinv, int* info, hipStream_t s) {
-  if (chol_waves() == 2)
-    hipLaunchKernelGGL(potrf_diag2_kernel<2>, dim3(1), dim3(128), 0, s, A, M, k0, Dinv, info);
-  else
-    hipLaunchKernelGGL(potrf_diag2_kernel<4>, dim3(1), dim3(256), 0, s, A, M, k0, Dinv, info);
+  hipLaunchKernelGGL(potrf_diag2_kernel<4>, dim3(1), dim3(256), 0, s, A, M, k0, Dinv, info);
 }
 
 // (MGP_CHOL_DIAG=block selects the 512-thread diagonal factor; a tuning
