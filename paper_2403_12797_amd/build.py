@@ -29,8 +29,19 @@ FLAGS = [
 ]
 
 
+# The FP64-MFMA sources: keep the accumulators of the MFMA tile loops in the
+# ordinary vector registers.  Otherwise the loop-carried accumulators live in
+# vector registers while the MFMAs take them in the accumulation registers,
+# and all of them are copied there and back around every K step (64 moves per
+# 16 MFMAs in the tile product, the accumulate chain drained each time).
+EXTRA = {
+    "fp64_path.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    "tables_vec.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
+
+
 def _compile(src: str, obj: str) -> None:
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
