@@ -478,71 +478,133 @@ __global__ void __launch_bounds__(64 * W) potrf_diag2_kernel(double* __restrict_
 // global memory (lda, ldb), k in [kb, ke), rows m >= mv / columns n >= nv and
 // k >= kv read as zero.  4 waves, each a 32x32 quarter (2x2 MFMA blocks).
 // BT: B is given transposed, as Bt[n][k] = B[k][n] with row pitch ldb.
-template <bool BT = false>
-__device__ __forceinline__ void tile_gemm64(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
-                                            int64_t ldb, int kb, int ke, int mv, int nv, int kv, double* As,
-                                            double* Bs, f64x4 (&acc)[2][2]) {
-  // K steps of 16; the next step's tiles are fetched into registers while
-  // the current one is multiplied (four A and four B values per thread).
+// K steps of 32: each thread fetches four pairs of consecutive A values and
+// four of B into registers while the previous step is multiplied, and stores
+// them to LDS as 16-byte writes, A as As[m][k] and Bt as Bs[n][k] (pitch 34),
+// a [k][n] B as Bs[k][n] (pitch 66).  In MFMA s (0..7) of a step, the lanes
+// of K-slot q (lane / 16) take k = 8 q + s (the sum over k in another order),
+// so a lane's eight A (and Bt) values of a step are contiguous in LDS and
+// come in 16-byte reads.  Full tiles (all rows and columns inside, the K
+// range whole steps) skip the per-element bounds checks.
+constexpr int kTgK = 32;                // K per step
+constexpr int kTgP = kTgK + 2;          // pitch of the [row][k] tiles
+constexpr int kTgPn = 64 + 2;           // pitch of the [k][n] tile
+constexpr int kTgLds = 64 * kTgP;       // LDS doubles per operand tile
+static_assert(kTgK * kTgPn <= kTgLds, "B tile");
+
+template <bool BT, bool FULL>
+__device__ __forceinline__ void tile_gemm64_run(const double* __restrict__ A, int64_t lda,
+                                                const double* __restrict__ B, int64_t ldb, int kb, int ke, int mv,
+                                                int nv, int kv, double* As, double* Bs, f64x4 (&acc)[2][2]) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wr = wv >> 1, wc = wv & 1;
-  double ra[4], rb[4];
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int kend = min(ke, kv);
+  double2 ra[4], rb[4];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int u = t + r * 256;
-      const int m = u >> 4, k = u & 15;
-      ra[r] = (m < mv && k0 + k < kv && k0 + k < ke) ? A[(int64_t)m * lda + k0 + k] : 0.0;
-      if constexpr (BT) {
-        rb[r] = (m < nv && k0 + k < kv && k0 + k < ke) ? B[(int64_t)m * ldb + k0 + k] : 0.0;   // Bt[n = m][k]
+      const int m = u >> 4, k = k0 + (u & 15) * 2;   // [row][k] tiles: row u / 16, k pair u % 16
+      const double* pa = A + (int64_t)m * lda + k;
+      if constexpr (FULL) {
+        ra[r].x = pa[0];
+        ra[r].y = pa[1];
       } else {
-        const int kk = u >> 6, nn = u & 63;
-        rb[r] = (nn < nv && k0 + kk < kv && k0 + kk < ke) ? B[(int64_t)(k0 + kk) * ldb + nn] : 0.0;
+        ra[r].x = (m < mv && k < kend) ? pa[0] : 0.0;
+        ra[r].y = (m < mv && k + 1 < kend) ? pa[1] : 0.0;
+      }
+      if constexpr (BT) {
+        const double* pb = B + (int64_t)m * ldb + k;
+        if constexpr (FULL) {
+          rb[r].x = pb[0];
+          rb[r].y = pb[1];
+        } else {
+          rb[r].x = (m < nv && k < kend) ? pb[0] : 0.0;
+          rb[r].y = (m < nv && k + 1 < kend) ? pb[1] : 0.0;
+        }
+      } else {
+        const int kk = k0 + (u >> 5), n = (u & 31) * 2;   // [k][n] tile: k u / 32, n pair u % 32
+        const double* pb = B + (int64_t)kk * ldb + n;
+        if constexpr (FULL) {
+          rb[r].x = pb[0];
+          rb[r].y = pb[1];
+        } else {
+          rb[r].x = (n < nv && kk < kend) ? pb[0] : 0.0;
+          rb[r].y = (n + 1 < nv && kk < kend) ? pb[1] : 0.0;
+        }
       }
     }
   };
-  if (kb < ke) fetch(kb);
-  for (int k0 = kb; k0 < ke; k0 += 16) {
+  fetch(kb);
+  for (int k0 = kb; k0 < ke; k0 += kTgK) {
     __syncthreads();
-    // A tile 64 x 16 -> As[m][k] (pitch 17), B tile 16 x 64 -> Bs[k][n] (pitch 66)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int u = t + r * 256;
-      As[(u >> 4) * 17 + (u & 15)] = ra[r];
+      *reinterpret_cast<double2*>(As + (u >> 4) * kTgP + (u & 15) * 2) = ra[r];
       if constexpr (BT)
-        Bs[(u & 15) * 66 + (u >> 4)] = rb[r];
+        *reinterpret_cast<double2*>(Bs + (u >> 4) * kTgP + (u & 15) * 2) = rb[r];
       else
-        Bs[(u >> 6) * 66 + (u & 63)] = rb[r];
+        *reinterpret_cast<double2*>(Bs + (u >> 5) * kTgPn + (u & 31) * 2) = rb[r];
     }
     __syncthreads();
-    if (k0 + 16 < ke) fetch(k0 + 16);
+    if (k0 + kTgK < ke) fetch(k0 + kTgK);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = kk * 4 + (lane >> 4);
-      double av[2], bv[2];
+    for (int h = 0; h < 2; ++h) {
+      // MFMAs s = 4 h .. 4 h + 3: lane values k = 8 kq + s
+      double av[2][4], bv[2][4];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        av[q] = As[(wr * 32 + q * 16 + (lane & 15)) * 17 + k];
-        bv[q] = Bs[k * 66 + wc * 32 + q * 16 + (lane & 15)];
+        const double* pa = As + (wr * 32 + q * 16 + i16) * kTgP + 8 * kq + 4 * h;
+        const double2 a0 = *reinterpret_cast<const double2*>(pa), a1 = *reinterpret_cast<const double2*>(pa + 2);
+        av[q][0] = a0.x;
+        av[q][1] = a0.y;
+        av[q][2] = a1.x;
+        av[q][3] = a1.y;
+        if constexpr (BT) {
+          const double* pb = Bs + (wc * 32 + q * 16 + i16) * kTgP + 8 * kq + 4 * h;
+          const double2 b0 = *reinterpret_cast<const double2*>(pb), b1 = *reinterpret_cast<const double2*>(pb + 2);
+          bv[q][0] = b0.x;
+          bv[q][1] = b0.y;
+          bv[q][2] = b1.x;
+          bv[q][3] = b1.y;
+        } else {
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) bv[q][s4] = Bs[(8 * kq + 4 * h + s4) * kTgPn + wc * 32 + q * 16 + i16];
+        }
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a][s4], bv[b][s4], acc[a][b]);
     }
   }
+}
+
+template <bool BT = false>
+__device__ __forceinline__ void tile_gemm64(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+                                            int64_t ldb, int kb, int ke, int mv, int nv, int kv, double* As,
+                                            double* Bs, f64x4 (&acc)[2][2]) {
+  if (kb >= ke) return;
+  if (mv >= 64 && nv >= 64 && kv >= ke && (ke - kb) % kTgK == 0)
+    tile_gemm64_run<BT, true>(A, lda, B, ldb, kb, ke, mv, nv, kv, As, Bs, acc);
+  else
+    tile_gemm64_run<BT, false>(A, lda, B, ldb, kb, ke, mv, nv, kv, As, Bs, acc);
 }
 
 // C = alpha A B^T (A: m x k, B: n x k, both row-major; C: m x n, pitch ldc),
 // one 64x64 tile of C per work-group on the pipelined FP64-MFMA tile
 // product.  b_lower: B is lower triangular (B[r][c] = 0 for c > r), so the
 // tile of columns n0.. needs k < n0 + 64 only.
-__global__ void __launch_bounds__(256) gemm_nt_f64_kernel(const double* __restrict__ A, int64_t lda,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) gemm_nt_f64_kernel(const double* __restrict__ A, int64_t lda,
                                                           const double* __restrict__ B, int64_t ldb,
                                                           double* __restrict__ C, int64_t ldc, int m, int n, int k,
                                                           double alpha, int b_lower) {
-  __shared__ double As[64 * 17];
-  __shared__ double Bs[16 * 66];
+  __shared__ __align__(16) double As[kTgLds];
+  __shared__ __align__(16) double Bs[kTgLds];
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int ke = b_lower ? min(k, n0 + 64) : k;
   f64x4 acc[2][2];
@@ -573,11 +635,11 @@ void launch_gemm_nt_f64(const double* A, int64_t lda, const double* B, int64_t l
 
 // Panel below the diagonal block: L21 = B21 L11^-T = B21 X^T as one 64x64x64
 // FP64-MFMA product per 64-row block (X lower, zero above the diagonal).
-__global__ void __launch_bounds__(256) trsm_panel_kernel(double* __restrict__ A, int M, int k0,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) trsm_panel_kernel(double* __restrict__ A, int M, int k0,
                                                          const double* __restrict__ Dinv,
                                                          const int* __restrict__ info) {
-  __shared__ double As[64 * 17];
-  __shared__ double Bs[16 * 66];
+  __shared__ __align__(16) double As[kTgLds];
+  __shared__ __align__(16) double Bs[kTgLds];
   if (*info) return;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wr = wv >> 1, wc = wv & 1;
@@ -607,10 +669,10 @@ __global__ void __launch_bounds__(256) trsm_panel_kernel(double* __restrict__ A,
 // factored columns of the tiles' rows, on the pipelined 64x64 FP64-MFMA tile
 // product (L_C read transposed).  Tiles are counted from row/column `base`:
 // tile columns cb <= C < ce, rows C <= R < T (the diagonal tiles whole).
-__global__ void __launch_bounds__(256) syrk_update_kernel(double* __restrict__ A, int M, int k0, int kw, int base,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) syrk_update_kernel(double* __restrict__ A, int M, int k0, int kw, int base,
                                                           int cb, int T, const int* __restrict__ info) {
-  __shared__ double As[64 * 17];
-  __shared__ double Bs[16 * 66];
+  __shared__ __align__(16) double As[kTgLds];
+  __shared__ __align__(16) double Bs[kTgLds];
   if (*info) return;
   int t = blockIdx.x, C = cb;
   while (t >= T - C) {
@@ -713,11 +775,11 @@ __global__ void trtri_diag_kernel(const double* __restrict__ Dinv, double* __res
 }
 
 // T[g] = L21 X11 for pair g of width b (T is b x b, row-major, per pair).
-__global__ void __launch_bounds__(256) trtri_merge_t_kernel(const double* __restrict__ L,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) trtri_merge_t_kernel(const double* __restrict__ L,
                                                             const double* __restrict__ X, double* __restrict__ T,
                                                             int M, int b, const int* __restrict__ info) {
-  __shared__ double As[64 * 17];
-  __shared__ double Bs[16 * 66];
+  __shared__ __align__(16) double As[kTgLds];
+  __shared__ __align__(16) double Bs[kTgLds];
   if (*info) return;
   const int g = blockIdx.z;
   const int o = 2 * g * b;          // first row/column of the pair
@@ -750,10 +812,10 @@ __global__ void __launch_bounds__(256) trtri_merge_t_kernel(const double* __rest
 }
 
 // X21 = -X22 T[g].
-__global__ void __launch_bounds__(256) trtri_merge_x_kernel(double* __restrict__ X, const double* __restrict__ T,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) trtri_merge_x_kernel(double* __restrict__ X, const double* __restrict__ T,
                                                             int M, int b, const int* __restrict__ info) {
-  __shared__ double As[64 * 17];
-  __shared__ double Bs[16 * 66];
+  __shared__ __align__(16) double As[kTgLds];
+  __shared__ __align__(16) double Bs[kTgLds];
   if (*info) return;
   const int g = blockIdx.z;
   const int o = 2 * g * b;
