@@ -669,17 +669,54 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) t
 // factored columns of the tiles' rows, on the pipelined 64x64 FP64-MFMA tile
 // product (L_C read transposed).  Tiles are counted from row/column `base`:
 // tile columns cb <= C < ce, rows C <= R < T (the diagonal tiles whole).
+// Tile j of the lower-triangle tile set {0 <= C <= R < T} in bands of 8
+// columns: band by band, row by row, the band's columns of each row.  A run
+// of consecutive tiles shares its 8 column panels and each row panel 8 times.
+__device__ __forceinline__ void band_tile(int j, int T, int& R, int& C) {
+  int g0 = 0;
+  for (;;) {
+    const int w = min(8, T - g0);
+    const int n = w * (w + 1) / 2 + (T - g0 - w) * w;
+    if (j < n) {
+      if (j < w * (w + 1) / 2) {
+        int r = 0;
+        while ((r + 1) * (r + 2) / 2 <= j) ++r;
+        R = g0 + r;
+        C = g0 + j - r * (r + 1) / 2;
+      } else {
+        j -= w * (w + 1) / 2;
+        R = g0 + w + j / w;
+        C = g0 + j % w;
+      }
+      return;
+    }
+    j -= n;
+    g0 += 8;
+  }
+}
+
+// XCD-aware order (banded = 1): blocks are dealt round-robin to the 8 XCDs,
+// so block b is given tile (b % 8) q + b / 8 (q = tiles / 8, the rest in
+// order) and each XCD runs one contiguous stretch of the banded order, its
+// panels shared in its own L2.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) syrk_update_kernel(double* __restrict__ A, int M, int k0, int kw, int base,
-                                                          int cb, int T, const int* __restrict__ info) {
+                                                          int cb, int T, int banded, const int* __restrict__ info) {
   __shared__ __align__(16) double As[kTgLds];
   __shared__ __align__(16) double Bs[kTgLds];
   if (*info) return;
-  int t = blockIdx.x, C = cb;
-  while (t >= T - C) {
-    t -= T - C;
-    ++C;
+  int R, C;
+  if (banded) {
+    const int nt = gridDim.x, q = nt / 8, b = blockIdx.x;
+    band_tile(b < 8 * q ? (b % 8) * q + b / 8 : b, T, R, C);
+  } else {
+    int t = blockIdx.x;
+    C = cb;
+    while (t >= T - C) {
+      t -= T - C;
+      ++C;
+    }
+    R = C + t;
   }
-  const int R = C + t;
   const int R0 = base + R * kNb, C0 = base + C * kNb;
   f64x4 acc[2][2];
 #pragma unroll
@@ -721,6 +758,13 @@ static bool chol_diag_block() {
   return v && strcmp(v, "block") == 0;
 }
 
+// The trailing update in the XCD-aware banded tile order (MGP_SYRK_ORDER=0
+// selects the plain column order; a tuning knob).
+static bool syrk_banded() {
+  const char* v = getenv("MGP_SYRK_ORDER");
+  return !(v && atoi(v) == 0);
+}
+
 // Two-level blocking: outer panels of kCholOuter columns, factored in
 // 64-column steps (diagonal block, panel solve below it, update of the
 // panel's remaining columns only); the trailing matrix right of an outer
@@ -746,13 +790,13 @@ void launch_cholesky(double* A, int M, double* Dinv, int* info, hipStream_t s) {
       const int ce = (int)ceil_div(kend - k0 - kNb, kNb);
       if (ce > 0)
         hipLaunchKernelGGL(syrk_update_kernel, dim3(update_tiles(0, ce, tb)), dim3(256), 0, s, A, M, k0, kNb,
-                           k0 + kNb, 0, tb, info);
+                           k0 + kNb, 0, tb, 0, info);
     }
     const int rest = M - kend;
     if (rest > 0) {
       const int T = (int)ceil_div(rest, kNb);
       hipLaunchKernelGGL(syrk_update_kernel, dim3(update_tiles(0, T, T)), dim3(256), 0, s, A, M, K0, kend - K0,
-                         kend, 0, T, info);
+                         kend, 0, T, syrk_banded() ? 1 : 0, info);
     }
   }
 }
