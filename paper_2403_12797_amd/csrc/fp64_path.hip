@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(kPfThreads) potrf_diag_kernel(double* __restri
 // formed.  r comes from the hardware estimate and two Newton steps.  A
 // failing pivot is recorded and replaced by 1 so the loop runs to the end
 // (what was written is then meaningless; info says so).  Rows and columns
-// past the matrix are the identity.
+// past the matrix are the identity; 8-step blocks wholly past it are skipped.
 constexpr int kPdNone = kNb + 1;
 constexpr int kD2Blk = 8;    // steps per unrolled block
 // Lt pitch for W waves of 64 / W columns: the owner's shifted registers reach
@@ -363,8 +363,11 @@ __global__ void __launch_bounds__(64 * W) potrf_diag2_kernel(double* __restrict_
   double l = 0.0, rk = 1.0;   // the owner's next column of L and its 1/L[K][K]
   double lp = 0.0;            // the owner's previous column, whose rank-1 update is pending
   double xp = 0.0;            // the owner's previous row of X, whose update is pending
+  // blocks of 8 steps holding columns of the matrix; the rest of the block
+  // is the identity, nothing to factor (its rows of X are zero below)
+  const int nbb = (nb + kD2Blk - 1) / kD2Blk;
 #pragma unroll 1
-  for (int b = 0; b < kNb / kD2Blk; ++b) {
+  for (int b = 0; b < nbb; ++b) {
     const int K0 = kD2Blk * b;
     if (b / BPW == H) {
       const bool first_blk = b % BPW == 0;
@@ -469,6 +472,7 @@ __global__ void __launch_bounds__(64 * W) potrf_diag2_kernel(double* __restrict_
       }
     }
   }
+  for (int r = kD2Blk * nbb + H; r < kNb; r += W) D[r * kNb + i] = 0.0;
   if (bad && i == 0) atomicMin(&sbad, bad);
   __syncthreads();
   if (sbad != kPdNone && t == 0) *info = k0 + sbad;
