@@ -269,7 +269,10 @@ gp_status gp_autotune(gp_ctx *ctx, int32_t p, int32_t n, int64_t N, int32_t *chu
  *         mean/var), GP_REQ_FIT_PREDICT (both; the model is kept only if
  *         model_out is requested at poll time, else freed).
  * All arrays are device arrays as above and must stay valid until gp_poll
- * has returned a final (non-PENDING) status for the request.  Requests are
+ * has returned a final (non-PENDING) status for the request.  Requests run
+ * on the context's own streams, ordered after nothing of the caller's: the
+ * work that writes x, y, xs (or that still touches mean, var) must be
+ * complete when gp_submit is called (synchronise its stream first).  Requests are
  * admitted when their device footprint fits what the context's HBM budget
  * has left (the budget less the bytes of admitted requests and of served
  * models not yet freed); work of admitted requests overlaps on the device.

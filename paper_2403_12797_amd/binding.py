@@ -322,6 +322,9 @@ class Context:
         return mb.value, tb.value
 
     def submit(self, kind, *, x=None, y=None, params=None, model=None, xs=None, mean=None, var=None) -> int:
+        """gp_submit.  The request runs on the context's own streams: work that
+        writes the tensors (or still uses mean/var) must be complete first,
+        e.g. after torch.cuda.current_stream().synchronize()."""
         req = _request(kind, x=x, y=y, params=params, model=model, xs=xs, mean=mean, var=var)
         rid = C.c_int64()
         _check(load().gp_submit(self.handle, C.byref(req), C.byref(rid)))

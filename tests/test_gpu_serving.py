@@ -37,6 +37,9 @@ def submit(ctx, torch, P, prec, keep):
     mean = torch.full((P.Ns,), float("nan"), dtype=torch.float64, device="cuda")
     var = torch.full((P.Ns,), float("nan"), dtype=torch.float64, device="cuda")
     prm = B.make_params(P.p, P.n, P.sigma, P.eps, P.alpha, prec)
+    # requests run on the context's own streams: the fills above must be done
+    # before the request can write its outputs
+    torch.cuda.current_stream().synchronize()
     rid = ctx.submit(B.REQ_FIT_PREDICT, x=x, y=y, params=prm, xs=xs, mean=mean, var=var)
     keep.append((x, y, xs, prm))
     return rid, mean, var
@@ -193,11 +196,13 @@ def test_held_models_charged_and_out_of_order_admission(torch_cuda):
         assert np.all(np.isfinite(held.weights()))
         mean_G = torch.full((G.Ns,), float("nan"), dtype=torch.float64, device="cuda")
         var_G = torch.full_like(mean_G, float("nan"))
+        torch.cuda.current_stream().synchronize()
         gid = ctx.submit(B.REQ_FIT_PREDICT, **req(G, B.REQ_FIT_PREDICT), mean=mean_G, var=var_G)
         outs = []
         for P in smalls:
             mean = torch.full((P.Ns,), float("nan"), dtype=torch.float64, device="cuda")
             var = torch.full_like(mean, float("nan"))
+            torch.cuda.current_stream().synchronize()
             outs.append((ctx.submit(B.REQ_FIT_PREDICT, **req(P, B.REQ_FIT_PREDICT), mean=mean, var=var), mean, var))
         for sid, _, _ in outs:                        # admitted ahead of G
             st, _ = ctx.poll(sid, wait_us=-1)
