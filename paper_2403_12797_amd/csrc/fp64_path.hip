@@ -905,7 +905,8 @@ size_t trtri_workspace_elems(int M) {
 
 void launch_trtri(const double* L, const double* Dinv, double* Linv, double* ws, int M, const int* info,
                   hipStream_t s) {
-  launch_fill_zero_f64(Linv, (int64_t)M * M, s);
+  // (one diagonal block writes every entry, zeros above the diagonal included)
+  if (M > kNb) launch_fill_zero_f64(Linv, (int64_t)M * M, s);
   const int nblk = (int)ceil_div(M, kNb);
   hipLaunchKernelGGL(trtri_diag_kernel, dim3(nblk), dim3(256), 0, s, Dinv, Linv, M);
   for (int b = kNb; b < M; b *= 2) {
@@ -960,8 +961,10 @@ void launch_lower_matvec(const double* Linv, const double* b, double* z, int M, 
 
 void launch_lower_t_matvec(const double* Linv, const double* z, double* w, double* part, int M, hipStream_t s) {
   const int chunks = (int)ceil_div(M, kLtChunk);
-  hipLaunchKernelGGL(lower_t_part_kernel, dim3(ceil_div(M, 256), chunks), dim3(256), 0, s, Linv, z, part, M);
-  hipLaunchKernelGGL(sum_parts_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part, chunks, M, w);
+  // one row chunk: its partial is the result (no second launch)
+  hipLaunchKernelGGL(lower_t_part_kernel, dim3(ceil_div(M, 256), chunks), dim3(256), 0, s, Linv, z,
+                     chunks == 1 ? w : part, M);
+  if (chunks > 1) hipLaunchKernelGGL(sum_parts_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part, chunks, M, w);
 }
 
 // ================================================================ a5 FP64 variance

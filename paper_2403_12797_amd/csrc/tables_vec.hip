@@ -460,6 +460,11 @@ void launch_phiT_vec(const double* x, const double* v, int64_t N, int p, int n, 
     default: hipLaunchKernelGGL(phiT_gemm_kernel<4>, grid, dim3(256), lds, s, x, v, N, p, n, M, chunk, tab, part); break;
   }
   const int64_t G = phiT_groups(chunks), per = ceil_div(chunks, G);
+  if (per == 1) {
+    // groups of one chunk: the group pass would only copy the rows
+    hipLaunchKernelGGL(reduce_cols_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part, chunks, M, sub, wsub, out);
+    return;
+  }
   hipLaunchKernelGGL(reduce_cols_group_kernel, dim3(ceil_div(M, 256), ceil_div(chunks, per)), dim3(256), 0, s, part,
                      chunks, per, M);
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part + chunks * (int64_t)M,
