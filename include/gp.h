@@ -241,8 +241,9 @@ gp_status gp_learn(gp_ctx *ctx, const gp_params *start, const double *x, const d
  * params/x/y/N/out_models are arrays of length count (x[k], y[k] device
  * arrays as in gp_fit).  The mixed-precision problems of each Gram scheme
  * share one persistent Gram launch over all their tiles (work list, longest
- * first); the whole
- * batch runs as one captured HIP graph.  Waits for completion.  Each
+ * first); the per-problem work runs on four forked streams (enqueued
+ * directly; MGP_BATCH_GRAPH=1 captures the whole batch in one HIP graph
+ * first, the same results).  Waits for completion.  Each
  * out_models[k] is a new model; on an error the failing problem's model is
  * NULL and the first error is returned (other models stay valid).
  * Errors: as gp_fit, with the problem index in the message.               */

@@ -1,5 +1,6 @@
 """Batched fit/predict (gp_fit_batch / gp_predict_batch, one persistent Gram
-launch for all mixed problems, captured graph) and the autotuner.
+launch for all mixed problems, direct launches or one captured graph) and the
+autotuner.
 
 * every batched result equals the same problem fitted alone (bitwise: the
   batch uses the same per-problem chunking and reduction order);
@@ -87,6 +88,28 @@ def test_batch_equals_single_and_oracle(torch_cuda, prec):
                 assert_within(ev, TOL64, "variance")
         for m in models:
             m.free()
+
+
+def test_batch_graph_equals_direct(torch_cuda, monkeypatch):
+    """The batch captured in one HIP graph (MGP_BATCH_GRAPH=1) gives the same
+    models bitwise as the default direct launches."""
+    torch = torch_cuda
+    Ps = batch_problems(12)
+    precs = [(B.PREC_MIXED_F16, B.PREC_MIXED, B.PREC_FP64)[k % 3] for k in range(len(Ps))]
+    with B.Context(0) as ctx:
+        xs = [(dev(torch, P.x), dev(torch, P.y)) for P in Ps]
+        probs = [(x, y, P.p, P.n, P.sigma, P.eps, P.alpha) for (x, y), P in zip(xs, Ps)]
+        got = {}
+        for mode in ("0", "1"):
+            monkeypatch.setenv("MGP_BATCH_GRAPH", mode)
+            models = ctx.fit_batch(probs, precision=precs)
+            torch.cuda.synchronize()
+            got[mode] = [(m.get(B.MODEL_W), m.get(B.MODEL_LINV)) for m in models]
+            for m in models:
+                m.free()
+    for k, P in enumerate(Ps):
+        print(f"[case] batch graph/direct {P.name} prec={precs[k]}", flush=True)
+        assert np.array_equal(got["0"][k][0], got["1"][k][0]) and np.array_equal(got["0"][k][1], got["1"][k][1])
 
 
 def test_batch_failure_isolated(torch_cuda):
