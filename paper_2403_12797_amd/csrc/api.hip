@@ -111,7 +111,6 @@ FitLayout fit_layout(int64_t N, int p, int n, int64_t M, int precision, int chun
   L.resid = take((size_t)N * 8);
   L.z = take((size_t)M * 8);
   L.r = take((size_t)M * 8);
-  L.d = take((size_t)M * 8);
   L.ltpart = take((size_t)ceil_div(M, 256) * M * 8);
   L.trws = take(trtri_workspace_elems((int)M) * 8);
   L.lmlpart = take(kLmlParts * 8);
@@ -240,8 +239,7 @@ void enqueue_fit_head(gp_model* m, const double* x, const double* y, int64_t N, 
   }
   char* wb = (char*)ws;
   launch_fill_zero_int(m->flags, 16, s);
-  launch_check_finite(x, N * p, m->flags + 1, s);
-  launch_check_finite(y, N, m->flags + 1, s);
+  launch_check_finite(x, N * p, y, N, m->flags + 1, s);
   launch_eig_tables(a, m->tab, m->lam, m->reg, M, s);
   launch_midx(p, n, M, m->midx, s);
   if (prec_mixed(m->precision)) launch_pdesc(p, n, M, m->pdesc, s);
@@ -257,7 +255,6 @@ void enqueue_fit_tail(gp_model* m, const double* x, const double* y, int64_t N, 
   double* resid = (double*)(wb + L.resid);
   double* z = (double*)(wb + L.z);
   double* r = (double*)(wb + L.r);
-  double* d = (double*)(wb + L.d);
   double* ltpart = (double*)(wb + L.ltpart);
   double* trws = (double*)(wb + L.trws);
   Prof* pr = &m->ctx->prof;
@@ -277,8 +274,7 @@ void enqueue_fit_tail(gp_model* m, const double* x, const double* y, int64_t N, 
   launch_phi_matvec(x, N, p, n, M, m->tab, m->midx, m->w, y, resid, s);                 // y - Phi w
   launch_phiT_vec(x, resid, N, p, n, M, m->tab, vpart, m->reg, m->w, r, s);    // Phi^T(y - Phi w) - reg*w
   launch_lower_matvec(m->Linv, r, z, M, s);
-  launch_lower_t_matvec(m->Linv, z, d, ltpart, M, s);
-  launch_axpy(m->w, d, M, s);
+  launch_lower_t_matvec(m->Linv, z, m->w, ltpart, M, s, m->w);   // w += L^-T z
   // y^T y, log det L, sum log Lambda, b^T w and the log marginal likelihood
   launch_fit_stats(y, N, m->b, m->w, m->L, m->lam, M, m->sigma, (double*)(wb + L.lmlpart), m->stats, s);
   prof_mark(pr, GP_PH_SOLVE, false, s);

@@ -937,34 +937,36 @@ __global__ void __launch_bounds__(256) lower_matvec_kernel(const double* __restr
 constexpr int kLtChunk = 256;
 __global__ void __launch_bounds__(256) lower_t_part_kernel(const double* __restrict__ Li,
                                                            const double* __restrict__ z,
-                                                           double* __restrict__ part, int M) {
+                                                           double* part, int M, const double* add) {
   const int c = blockIdx.x * 256 + threadIdx.x;
   const int rc = blockIdx.y;
   if (c >= M) return;
   double s = 0.0;
   const int rs = max(rc * kLtChunk, c), re = min((rc + 1) * kLtChunk, M);
   for (int r = rs; r < re; ++r) s = fma(Li[(int64_t)r * M + c], z[r], s);
-  part[(int64_t)rc * M + c] = s;
+  part[(int64_t)rc * M + c] = add ? add[c] + s : s;
 }
 
-__global__ void sum_parts_kernel(const double* __restrict__ part, int chunks, int M, double* __restrict__ w) {
+__global__ void sum_parts_kernel(const double* __restrict__ part, int chunks, int M, double* w, const double* add) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= M) return;
   double s = 0.0;
   for (int k = 0; k < chunks; ++k) s += part[(int64_t)k * M + c];
-  w[c] = s;
+  w[c] = add ? add[c] + s : s;
 }
 
 void launch_lower_matvec(const double* Linv, const double* b, double* z, int M, hipStream_t s) {
   hipLaunchKernelGGL(lower_matvec_kernel, dim3(ceil_div(M, 4)), dim3(256), 0, s, Linv, b, z, M);
 }
 
-void launch_lower_t_matvec(const double* Linv, const double* z, double* w, double* part, int M, hipStream_t s) {
+void launch_lower_t_matvec(const double* Linv, const double* z, double* w, double* part, int M, hipStream_t s,
+                           const double* add) {
   const int chunks = (int)ceil_div(M, kLtChunk);
   // one row chunk: its partial is the result (no second launch)
   hipLaunchKernelGGL(lower_t_part_kernel, dim3(ceil_div(M, 256), chunks), dim3(256), 0, s, Linv, z,
-                     chunks == 1 ? w : part, M);
-  if (chunks > 1) hipLaunchKernelGGL(sum_parts_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part, chunks, M, w);
+                     chunks == 1 ? w : part, M, chunks == 1 ? add : nullptr);
+  if (chunks > 1)
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, part, chunks, M, w, add);
 }
 
 // ================================================================ a5 FP64 variance

@@ -103,10 +103,10 @@ void launch_trtri(const double* L, const double* Dinv, double* Linv, double* ws,
                   const int* info, hipStream_t s);
 // z = Linv b ; w = Linv^T z  (both through `tmp`, M doubles)
 void launch_lower_matvec(const double* Linv, const double* b, double* z, int M, hipStream_t s);
+// (w = add + Linv^T z when add is given; add may be w itself)
 void launch_lower_t_matvec(const double* Linv, const double* z, double* w, double* part, int M,
-                           hipStream_t s);
+                           hipStream_t s, const double* add = nullptr);
 // w += d
-void launch_axpy(double* w, const double* d, int M, hipStream_t s);
 // Split of L^-1 into two bf16 terms (mixed predict): pieces[q][M][P] with
 // row pitch P = linv_pitch(M) (multiple of 16, padding columns zero).
 __host__ __device__ inline int linv_pitch(int M) { return (M + 15) & ~15; }
@@ -150,7 +150,8 @@ void launch_fill_zero_int(int* p, int count, hipStream_t s);
 void launch_fill_zero_f64(double* p, int64_t count, hipStream_t s);
 
 // Device check that every element of v[count] is finite; sets *flag = 1 if not.
-void launch_check_finite(const double* v, int64_t count, int* flag, hipStream_t s);
+// flag = 1 if any of a[0..na) or b[0..nb) is not finite (one launch)
+void launch_check_finite(const double* a, int64_t na, const double* b, int64_t nb, int* flag, hipStream_t s);
 
 // Raise the dynamic-LDS limit of the kernels that need more than 64 KB.
 hipError_t configure_kernels();

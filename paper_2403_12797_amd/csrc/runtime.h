@@ -45,7 +45,7 @@ namespace mgp {
 // (byte offsets).  all_splits keeps every Gram partial (no passes).
 struct FitLayout {
   GramPlan g;
-  size_t gpart, tab32, hbuf, vpart, resid, z, r, d, ltpart, trws, lmlpart, total;
+  size_t gpart, tab32, hbuf, vpart, resid, z, r, ltpart, trws, lmlpart, total;
   bool lean;
   size_t A, Dinv, Linv;  // lean models only: A (factored in place), Dinv, L^-1 (mixed)
 };

@@ -472,18 +472,20 @@ void launch_phiT_vec(const double* x, const double* v, int64_t N, int p, int n, 
 }
 
 // ---------------------------------------------------------------- input checks
-__global__ void check_finite_kernel(const double* __restrict__ v, int64_t count, int* __restrict__ flag) {
+__global__ void check_finite_kernel(const double* __restrict__ a, int64_t na, const double* __restrict__ b,
+                                    int64_t nb, int* __restrict__ flag) {
   bool bad = false;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    bad |= !isfinite(v[i]);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(i < na ? a[i] : b[i - na]);
   if (__any(bad) && (threadIdx.x & 63) == 0) *flag = 1;
 }
 
-void launch_check_finite(const double* v, int64_t count, int* flag, hipStream_t s) {
+void launch_check_finite(const double* a, int64_t na, const double* b, int64_t nb, int* flag, hipStream_t s) {
+  const int64_t count = na + nb;
   if (count <= 0) return;
   int64_t blocks = ceil_div(count, 256);
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(check_finite_kernel, dim3(blocks), dim3(256), 0, s, v, count, flag);
+  hipLaunchKernelGGL(check_finite_kernel, dim3(blocks), dim3(256), 0, s, a, na, b, nb, flag);
 }
 
 // ---------------------------------------------------------------- fills (kernels, not memset nodes)
@@ -503,16 +505,6 @@ void launch_fill_zero_f64(double* p, int64_t count, hipStream_t s) {
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(fill_zero_f64_kernel, dim3(blocks), dim3(256), 0, s, p, count);
-}
-
-// ---------------------------------------------------------------- small vector ops
-__global__ void axpy_kernel(double* __restrict__ w, const double* __restrict__ d, int M) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m < M) w[m] += d[m];
-}
-
-void launch_axpy(double* w, const double* d, int M, hipStream_t s) {
-  hipLaunchKernelGGL(axpy_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, s, w, d, M);
 }
 
 }  // namespace mgp
