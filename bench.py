@@ -188,8 +188,8 @@ def batched_leg(torch, count, steps=2):
     one n ~ U{4..12} per problem, N log-uniform in [1e3, 2e5], N* = N,
     x ~ N(0, I_p), y = sum_d sin(k_d x_d) + N(0, 0.1^2), eps ~ U[0.5, 2],
     alpha = 1, sigma = 0.1; mixed precision (FP16 Gram).  A step is one
-    gp_fit_batch (one persistent Gram launch per kernel group, the rest in a
-    captured graph) and one gp_predict_batch over all problems, inputs
+    gp_fit_batch (one persistent Gram launch per kernel group, the rest on
+    four forked streams) and one gp_predict_batch over all problems, inputs
     resident in HBM; value = sum(N + N*) / seconds per step."""
     from paper_2403_12797_amd import binding as B
     from paper_2403_12797_amd import workloads as wl

@@ -756,7 +756,7 @@ static void launch_diag2(double* A, int M, int k0, double* Dinv, int* info, hipS
 }
 
 // (MGP_CHOL_DIAG=block selects the 512-thread diagonal factor; a tuning
-// knob, the two-wave factor is the default: 4 % faster Cholesky at M = 7776)
+// knob, the register-resident four-wave factor is the default)
 static bool chol_diag_block() {
   const char* v = getenv("MGP_CHOL_DIAG");
   return v && strcmp(v, "block") == 0;
