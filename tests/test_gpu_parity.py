@@ -126,6 +126,23 @@ def test_factor_stages_multiblock(torch_cuda, ctx, seed, p, n, N):
     assert E.max() <= 1e-12
 
 
+@pytest.mark.parametrize("knob", [("MGP_SYRK_ORDER", "0"), ("MGP_CHOL_DIAG", "block")])
+def test_factor_stages_alternative_paths(torch_cuda, ctx, monkeypatch, knob):
+    """The non-default factorisation paths behind the tuning knobs: the
+    trailing update in plain column order, and the 512-thread diagonal
+    factor (M = 2025: eight outer panels, a ragged last block)."""
+    monkeypatch.setenv(*knob)
+    P = wl.random_problem(28, 2, 45, 8000, 10)
+    m, _, _ = gpu_fit_predict(torch_cuda, ctx, P, B.PREC_FP64)
+    A = m.get(B.MODEL_A)
+    L = m.get(B.MODEL_L)
+    Li = m.get(B.MODEL_LINV)
+    assert rel(L @ L.T, A) <= 1e-13
+    E = np.abs(Li @ L - np.eye(P.M)) / (np.abs(Li) @ np.abs(L) + 1e-300)
+    print(f"[err] stages {knob[0]}={knob[1]} {P.name}: max |Li L - I| / (|Li||L|) = {E.max():.3e}", flush=True)
+    assert E.max() <= 1e-12
+
+
 @pytest.mark.parametrize("seed,p,n,N,Ns", [
     (1, 1, 1, 1, 1),          # smallest problem
     (2, 1, 7, 5, 3),          # M > N
