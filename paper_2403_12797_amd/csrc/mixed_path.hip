@@ -1060,8 +1060,11 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
   // L^-1 slab (rows r0..r0+255, columns c0..c0+15, both terms): 1024 uint4,
   // two per thread.  Rows past M read as zero; padding columns are zero.
   // (stage columns stay inside the pitch LP, a multiple of 16 >= M)
-  const int lr_r = (t >> 1) & 255;
-  const __bf16* const lbase0 = lpieces + (int64_t)lr_r * LP + (t & 1) * 8;   // term 0 (t < 512)
+  // thread t holds row lr_r, columns 8 lr_h .. +8: 16 consecutive lanes take
+  // 16 rows of one half, so their LDS stores fall on 16 distinct 16-byte bank
+  // groups (a wave still reads 32 whole rows)
+  const int lr_r = ((t >> 5) << 4) | (t & 15), lr_h = (t >> 4) & 1;
+  const __bf16* const lbase0 = lpieces + (int64_t)lr_r * LP + lr_h * 8;   // term 0 (t < 512)
   const __bf16* const lbase1 = lbase0 + PP;                                   // term 1
   // (rows are padded to a multiple of 256 with zeros; a look-ahead past the
   // last row block re-reads the last one)
@@ -1070,12 +1073,11 @@ __global__ void __launch_bounds__(kPmThreads) predict_var_mixed_kernel(
     r0 = *reinterpret_cast<const uint4*>(lbase0 + off);
     r1 = *reinterpret_cast<const uint4*>(lbase1 + off);
   };
-  // thread t stores its two uint4 at row (t >> 1) & 255, columns 8 (t & 1)
-  // .. +8 of term 0 and the same place of term 1
+  // thread t stores its two uint4 at row lr_r, columns 8 lr_h .. +8 of term 0
+  // and the same place of term 1
   auto lin_store = [&](__bf16* lin, const uint4& r0, const uint4& r1) {
-    const int r = (t >> 1) & 255, half = t & 1;
-    *reinterpret_cast<uint4*>(lin + pm_at(0, kPmTR, r, half * 8)) = r0;
-    *reinterpret_cast<uint4*>(lin + pm_at(1, kPmTR, r, half * 8)) = r1;
+    *reinterpret_cast<uint4*>(lin + pm_at(0, kPmTR, lr_r, lr_h * 8)) = r0;
+    *reinterpret_cast<uint4*>(lin + pm_at(1, kPmTR, lr_r, lr_h * 8)) = r1;
   };
 
   __syncthreads();  // tables ready
