@@ -106,7 +106,6 @@ void launch_lower_matvec(const double* Linv, const double* b, double* z, int M, 
 // (w = add + Linv^T z when add is given; add may be w itself)
 void launch_lower_t_matvec(const double* Linv, const double* z, double* w, double* part, int M,
                            hipStream_t s, const double* add = nullptr);
-// w += d
 // Split of L^-1 into two bf16 terms (mixed predict): pieces[q][M][P] with
 // row pitch P = linv_pitch(M) (multiple of 16, padding columns zero).
 __host__ __device__ inline int linv_pitch(int M) { return (M + 15) & ~15; }
